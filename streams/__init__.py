@@ -1,0 +1,131 @@
+"""Seeded synthetic data streams (rows = samples, columns = marginals).
+
+This module only draws random numbers: it holds none of the cumulant method's
+arithmetic, and both the HIP path and the oracle read the arrays it returns.
+
+Every generator is numpy ``Generator(PCG64)`` seeded with
+``SeedSequence([170106446, workload_id, sub])``, draws in FP64 and returns a
+row-major array; callers cast to the path's input type (FP32 paths round once,
+the oracle widens the same rounded values back to FP64).
+
+A stream of ``t + steps*p`` rows is laid out as: rows ``[0, t)`` form the first
+window; step ``w`` (1-based) appends ``rows[t+(w-1)p : t+wp]`` and drops the
+window's oldest rows ``rows[(w-1)p : wp]`` (the sliding window of Sec. 2.1).
+
+The workloads mirror the paper's setting (Sec. 4.2): a Gaussian window whose
+later updates come from a non-Gaussian copula with the same covariance.  The
+paper's own t-copula covariance is not given, so the covariance here is
+``A A^T/n + I`` with a seeded Gaussian A, and the copula is Gaussian with
+Student-t(6) and Exp(1) marginals standardized to that covariance's variances.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+SEED_ROOT = 170106446
+
+
+def rng_for(workload_id: int, sub: int = 0) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_ROOT, workload_id, sub])))
+
+
+def covariance(rng: np.random.Generator, n: int) -> np.ndarray:
+    A = rng.standard_normal((n, n))
+    return A @ A.T / n + np.eye(n)
+
+
+def gaussian_rows(rng, m: int, sigma: np.ndarray) -> np.ndarray:
+    L = np.linalg.cholesky(sigma)
+    z = rng.standard_normal((m, sigma.shape[0]))
+    return z @ L.T
+
+
+def copula_rows(rng, m: int, sigma: np.ndarray) -> np.ndarray:
+    """Gaussian copula with correlation of ``sigma``; columns ``< n/2`` get a
+    standardized Student-t(6) marginal, the rest a standardized Exp(1)
+    marginal, each scaled to the column's variance ``sigma[j, j]``."""
+    from scipy import special, stats
+
+    n = sigma.shape[0]
+    sd = np.sqrt(np.diag(sigma))
+    z = gaussian_rows(rng, m, sigma) / sd
+    x = np.empty_like(z)
+    h = n // 2
+    zt = z[:, :h]
+    # t quantile of Phi(z), evaluated in the tail that keeps precision
+    x[:, :h] = np.sign(zt) * stats.t.isf(special.ndtr(-np.abs(zt)), 6) / np.sqrt(1.5)
+    # Exp(1) quantile of Phi(z) is -log(1 - Phi(z)) = -log(Phi(-z))
+    x[:, h:] = -special.log_ndtr(-z[:, h:]) - 1.0
+    return x * sd
+
+
+def exp_sources(rng, m: int, n: int) -> np.ndarray:
+    return rng.exponential(1.0, (m, n)) - 1.0
+
+
+def haar_orthogonal(rng, n: int) -> np.ndarray:
+    G = rng.standard_normal((n, n))
+    Q, R = np.linalg.qr(G)
+    return Q * np.sign(np.diag(R))
+
+
+@dataclass
+class Stream:
+    name: str
+    n: int
+    d: int
+    b: int
+    t: int
+    p: int
+    steps: int
+    rows: np.ndarray  # (t + steps*p, n), FP64
+
+    def window(self) -> np.ndarray:
+        return self.rows[: self.t]
+
+    def step(self, w: int):
+        """(X_new, X_old) of step w = 1..steps."""
+        t, p = self.t, self.p
+        return self.rows[t + (w - 1) * p: t + w * p], self.rows[(w - 1) * p: w * p]
+
+    def current_window(self, w: int) -> np.ndarray:
+        """The window after step w (w = 0 is the first window)."""
+        return self.rows[w * self.p: w * self.p + self.t]
+
+
+def gaussian_stream(n=20, d=4, b=2, t=2000, p=100, steps=20, workload_id=1) -> Stream:
+    """Plain Gaussian stream: rows i.i.d. N(0, A A^T/n + I)."""
+    rng = rng_for(workload_id)
+    sigma = covariance(rng, n)
+    rows = gaussian_rows(rng, t + steps * p, sigma)
+    return Stream("gaussian", n, d, b, t, p, steps, rows)
+
+
+def regime_change_stream(n=60, d=4, b=4, t=20000, p=1000, steps=200, switch=None,
+                         workload_id=2) -> Stream:
+    """Gaussian window and updates up to step ``switch`` (default steps//2),
+    copula updates afterwards (the regime change of Sec. 4.2)."""
+    rng = rng_for(workload_id)
+    sigma = covariance(rng, n)
+    if switch is None:
+        switch = steps // 2
+    g = gaussian_rows(rng, t + switch * p, sigma)
+    c = copula_rows(rng, (steps - switch) * p, sigma)
+    return Stream("regime_change", n, d, b, t, p, steps, np.vstack([g, c]))
+
+
+def mixed_exp_stream(n=48, d=6, b=4, t=50000, p=2000, steps=50, workload_id=3) -> Stream:
+    """Rows S W with S i.i.d. standardized Exp(1) sources and W Haar-orthogonal."""
+    rng = rng_for(workload_id)
+    W = haar_orthogonal(rng, n)
+    S = exp_sources(rng, t + steps * p, n)
+    s = Stream("mixed_exp", n, d, b, t, p, steps, S @ W)
+    s.mixing = W
+    return s
+
+
+def stream_by_name(name: str, **kw) -> Stream:
+    return {"gaussian": gaussian_stream, "regime_change": regime_change_stream,
+            "mixed_exp": mixed_exp_stream}[name](**kw)
