@@ -1,0 +1,173 @@
+/*
+ * cum.h -- C-ABI of libcum: sliding-window cumulant tensors on MI355X (gfx950).
+ *
+ * Method: Domino & Gawron, "Algorithm for an arbitrary-order cumulant tensor
+ * calculation in a sliding window of data streams" (arXiv:1701.06446).
+ *
+ * Data convention (Sec. 2.1): a window X holds t rows (samples) of n columns
+ * (marginals), row-major.  Each update appends p new rows X_new and drops the
+ * window's p oldest rows X_old (the batches X_(+) and X_(-) of Sec. 2.1).
+ *
+ * Storage convention (Sec. 2.3 block structure, Alg. 5): an order-k tensor is
+ * kept as the blocks whose block multi-index j_1 <= ... <= j_k is
+ * non-decreasing, with nbar = ceil(n/b) blocks per mode; blocks are listed in
+ * lexicographic order of j; every block is a full b^k array of doubles,
+ * row-major in (a_1, ..., a_k) with a_1 slowest, holding the element at global
+ * indices i_m = j_m*b + a_m.  Columns past n are zero padding and their
+ * entries are exactly 0.  cum_num_blocks() gives the block count
+ * C(nbar + k - 1, k); an order-k pyramid holds cum_num_blocks(n,b,k) * b^k
+ * doubles.
+ *
+ * Estimators: raw plug-in moments m_i = (1/t) sum_rows prod x (Eq. (mom));
+ * cumulants by the moment-cumulant recursion over all set partitions
+ * (Alg. 3/4); no bias correction.
+ *
+ * Pointers: every input pointer may be host or device memory (detected with
+ * hipPointerGetAttributes).  Inputs are FP64 when prec == CUM_FP64 and FP32
+ * otherwise.  The caller owns every buffer it passes.  Host inputs are copied
+ * before the call returns.  Device inputs are read by work queued on the
+ * context's stream: keep them unchanged until that work has completed
+ * (stream order, or cum_sync()).  The library owns its device state until
+ * cum_free().
+ *
+ * Errors: every call returns CUM_OK (0) or a negative cum_status; nothing
+ * aborts or throws across this boundary.  Arguments are validated before any
+ * work is queued.  On a validation error the context's state is unchanged
+ * and the context stays usable.  After CUM_EDEVICE the state is undefined.
+ *
+ * Threads: one context must not be used from two threads at once; distinct
+ * contexts are independent.
+ */
+#ifndef CUM_H
+#define CUM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cum_ctx cum_ctx;
+
+/* Precision of the moment contraction (the combine and norms are always FP64).
+ *   CUM_FP64   - FP64 inputs, FP64 MFMA, FP64 compensated window sums.
+ *   CUM_FP32   - FP32 inputs, FP32 MFMA, FP32 compensated (hi+lo) sums.
+ *   CUM_BF16X3 - FP32 inputs; every Khatri-Rao operand is split into
+ *                RNE-rounded bf16 hi + lo parts and each product is taken as
+ *                hi*hi + hi*lo + lo*hi on bf16 MFMA with FP32 accumulation;
+ *                FP32 compensated sums. */
+typedef enum { CUM_FP64 = 0, CUM_FP32 = 1, CUM_BF16X3 = 2 } cum_prec;
+
+typedef enum {
+  CUM_OK = 0,
+  CUM_EINVAL = -1,     /* bad argument (range, NULL pointer, p > t, ...) */
+  CUM_ENOMEM = -2,     /* device or host allocation failed */
+  CUM_EDEVICE = -3,    /* a HIP runtime call failed */
+  CUM_ESTATE = -4,     /* context not initialised */
+  CUM_ENONFINITE = -5, /* reserved: non-finite input detected */
+  CUM_ESIZE = -6       /* output capacity too small, or shape beyond limits */
+} cum_status;
+
+/* Library limits: 1 <= d <= CUM_MAX_ORDER, 1 <= b <= n <= CUM_MAX_COLS. */
+#define CUM_MAX_ORDER 6
+#define CUM_MAX_COLS 255
+
+/*
+ * cum_init -- create a context and compute the moments M_1..M_d of the first
+ * window X (t x n, row-major), then its cumulants C_1..C_d and norms (Alg. 1,
+ * lines "Input"/"Calculate moments").  The window is contracted in chunks of
+ * at most 2048 rows, each folded into the compensated running sums.
+ *   ctx        out: the new context (set to NULL on error)
+ *   n, d, b    columns (1..255), maximal order (1..6), block size
+ *              (1..n; b need not divide n: columns are zero-padded to
+ *              ceil(n/b)*b)
+ *   X          t x n window, FP64 if prec == CUM_FP64 else FP32
+ *   t          window length (>= 1)
+ *   prec       cum_prec
+ *   hip_stream hipStream_t for all work of this context (NULL = null stream)
+ */
+int cum_init(cum_ctx **ctx, int n, int d, int b, const void *X, int64_t t, int prec,
+             void *hip_stream);
+
+/*
+ * cum_update -- slide the window by p rows: M_k += (sum over X_new of x^(k) -
+ * sum over X_old of x^(k)) / t for k = 1..d (Eq. (momupdate), Alg. 2), then
+ * recompute C_1..C_d (Alg. 3/4) and the norms (Alg. 5, Eq. (mef)).
+ * Asynchronous on the context's stream.
+ *   X_new  p x n rows entering the window
+ *   X_old  p x n rows leaving it; precondition (not checked): these are the
+ *          window's p oldest rows
+ *   p      0 <= p <= t; p == 0 is a no-op
+ */
+int cum_update(cum_ctx *ctx, const void *X_new, const void *X_old, int64_t p);
+
+/*
+ * cum_get -- copy the order-k cumulant pyramid C_k (k = 1..d, FP64, layout
+ * above) into `blocks` (host or device), which holds `capacity_elems`
+ * doubles.  Synchronises the context's stream.  CUM_ESIZE if too small.
+ */
+int cum_get(cum_ctx *ctx, int k, double *blocks, size_t capacity_elems);
+
+/*
+ * cum_get_moments -- copy M_k = S_k / t (the running sums divided by the
+ * window length, FP64) in the same layout.  Synchronises.
+ */
+int cum_get_moments(cum_ctx *ctx, int k, double *blocks, size_t capacity_elems);
+
+/*
+ * cum_norms -- fro[k] = ||C_k||_F over the full n^k tensor (Alg. 5 with
+ * exponent 2) for k = 1..d, fro[0] = NaN; nu[k] = fro[k] / fro[2]^(k/2) for
+ * 3 <= k <= d (Eq. (mef)), NaN for k < 3 (and NaN when ||C_2|| = 0).  Both
+ * arrays hold d+1 doubles (host pointers).  Synchronises.
+ */
+int cum_norms(cum_ctx *ctx, double *fro, double *nu);
+
+/*
+ * cum_norms_device -- device address of the norms written by the last
+ * init/update: 2(d+1) doubles, fro[0..d] then nu[0..d].  Does not
+ * synchronise; the buffer is owned by the context and overwritten by the
+ * next update.
+ */
+int cum_norms_device(cum_ctx *ctx, const double **dev_ptr);
+
+/* cum_sync -- wait for all work queued on the context's stream. */
+int cum_sync(cum_ctx *ctx);
+
+/* cum_free -- release the context and its device state; NULL is allowed. */
+int cum_free(cum_ctx *ctx);
+
+/* Block count of an order-k pyramid, C(ceil(n/b) + k - 1, k); -1 on bad args. */
+int64_t cum_num_blocks(int n, int b, int k);
+
+/* Stored doubles of an order-k pyramid, cum_num_blocks(n,b,k) * b^k. */
+int64_t cum_num_elems(int n, int b, int k);
+
+/* Static text for a status code. */
+const char *cum_strerror(int status);
+
+/* Text naming the last failing HIP call of the calling thread (empty if none);
+ * valid until that thread's next failing call. */
+const char *cum_last_error(void);
+
+/*
+ * cum_plan_coverage -- host-only check of the update's pivot decomposition
+ * (no GPU needed): for order k, counts how many (pivot, row, column)
+ * products of the update land on each stored element (written to `hits`,
+ * cum_num_elems(n,b,k) ints, may be NULL) and returns the number of products
+ * that miss the pyramid or land on an element with other global indices
+ * (0 when the decomposition is exact), or a negative status.
+ */
+int64_t cum_plan_coverage(int n, int b, int k, int32_t *hits);
+
+/*
+ * cum_plan_items -- number of update workgroups (tiles) one update of
+ * orders 1..d launches; a negative status on bad arguments.  Host only.
+ */
+int64_t cum_plan_items(int n, int d, int b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CUM_H */

@@ -1,0 +1,202 @@
+"""Sliding-window cumulant tensors on MI355X (gfx950): Python binding of libcum.
+
+Thin ctypes binding over the C-ABI declared in ``include/cum.h``; every step of
+the method (moment update, cumulant combine, norms) runs in the library's HIP
+kernels.  The functions keep the C names:
+
+    ctx = cum_init(n, d, b, X, prec="fp32")      # first window, t x n rows
+    cum_update(ctx, X_new, X_old)                 # slide by p rows
+    C4 = cum_get(ctx, 4)                          # order-4 pyramid, FP64
+    fro, nu = cum_norms(ctx)                      # ||C_k||_F and nu_k
+    cum_free(ctx)
+
+Arrays may be numpy arrays (host) or torch tensors (host or device); they are
+passed by pointer, so they must be C-contiguous with the path's input dtype
+(float64 for "fp64", float32 for "fp32" and "bf16x3").  There is no fallback:
+importing this package fails if ``libcum.so`` has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcum.so")
+
+CUM_FP64, CUM_FP32, CUM_BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": CUM_FP64, "fp32": CUM_FP32, "bf16x3": CUM_BF16X3}
+CUM_OK, CUM_EINVAL, CUM_ENOMEM, CUM_EDEVICE, CUM_ESTATE, CUM_ENONFINITE, CUM_ESIZE = 0, -1, -2, -3, -4, -5, -6
+
+EXPORTS = ("cum_init", "cum_update", "cum_get", "cum_get_moments", "cum_norms",
+           "cum_norms_device", "cum_sync", "cum_free", "cum_num_blocks", "cum_num_elems",
+           "cum_strerror", "cum_last_error", "cum_plan_coverage", "cum_plan_items")
+
+
+class CumError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        detail = _lib.cum_last_error().decode() if status == CUM_EDEVICE else ""
+        super().__init__("%s: %s (status %d) %s" % (where, _lib.cum_strerror(status).decode(),
+                                                    status, detail))
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libcum.so is not built (run __graft_entry__.build() or "
+                          "python paper_1701_06446_amd/build.py): %s" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
+    pd = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "cum_init": (i32, [ctypes.POINTER(vp), i32, i32, i32, vp, i64, i32, vp]),
+        "cum_update": (i32, [vp, vp, vp, i64]),
+        "cum_get": (i32, [vp, i32, vp, sz]),
+        "cum_get_moments": (i32, [vp, i32, vp, sz]),
+        "cum_norms": (i32, [vp, pd, pd]),
+        "cum_norms_device": (i32, [vp, ctypes.POINTER(vp)]),
+        "cum_sync": (i32, [vp]),
+        "cum_free": (i32, [vp]),
+        "cum_num_blocks": (i64, [i32, i32, i32]),
+        "cum_num_elems": (i64, [i32, i32, i32]),
+        "cum_strerror": (ctypes.c_char_p, [i32]),
+        "cum_last_error": (ctypes.c_char_p, []),
+        "cum_plan_coverage": (i64, [i32, i32, i32, ctypes.POINTER(ctypes.c_int32)]),
+        "cum_plan_items": (i64, [i32, i32, i32]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+# torch's HIP runtime and the system one share the soname libamdhip64.so.7, but
+# torch's own modules ask for the unversioned name: loading libcum.so first
+# would put two runtimes in one process.  Import torch first (when present) so
+# that libcum.so binds to the runtime that owns torch's device memory.
+try:
+    import torch as _torch  # noqa: F401
+except ImportError:  # plain C-ABI use without torch
+    _torch = None
+
+_lib = _load()
+
+
+def _check(rc: int, where: str):
+    if rc != CUM_OK:
+        raise CumError(rc, where)
+
+
+def _dtype_for(prec: int):
+    return np.float64 if prec == CUM_FP64 else np.float32
+
+
+def _pointer(X, prec: int, ncols: int):
+    """(address, rows, keep-alive) of a C-contiguous numpy array or torch tensor."""
+    want = _dtype_for(prec)
+    if hasattr(X, "data_ptr"):  # torch tensor
+        import torch
+
+        tdt = torch.float64 if want is np.float64 else torch.float32
+        if X.dtype != tdt or not X.is_contiguous() or X.dim() != 2 or X.shape[1] != ncols:
+            raise ValueError("expected a contiguous %s tensor with %d columns" % (tdt, ncols))
+        return X.data_ptr(), int(X.shape[0]), X
+    A = np.asarray(X)
+    if A.dtype != want or not A.flags["C_CONTIGUOUS"] or A.ndim != 2 or A.shape[1] != ncols:
+        raise ValueError("expected a C-contiguous %s array with %d columns" % (np.dtype(want), ncols))
+    return A.ctypes.data, int(A.shape[0]), A
+
+
+class Context:
+    """Owns one ``cum_ctx``; released by ``cum_free`` (or garbage collection)."""
+
+    def __init__(self, handle, n, d, b, t, prec):
+        self.handle, self.n, self.d, self.b, self.t, self.prec = handle, n, d, b, t, prec
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.cum_free(self.handle)
+            self.handle = None
+
+
+def cum_init(n: int, d: int, b: int, X, prec="fp32", stream=None) -> Context:
+    """Moments, cumulants and norms of the first window X (t x n)."""
+    p = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+    addr, t, _keep = _pointer(X, p, n)
+    h = ctypes.c_void_p()
+    st = None if stream is None else ctypes.c_void_p(int(stream))
+    _check(_lib.cum_init(ctypes.byref(h), n, d, b, addr, t, p, st), "cum_init")
+    return Context(h, n, d, b, t, p)
+
+
+def cum_update(ctx: Context, X_new, X_old):
+    """Slide the window: X_new enters, X_old (the p oldest rows) leaves."""
+    an, pn, _k1 = _pointer(X_new, ctx.prec, ctx.n)
+    ao, po, _k2 = _pointer(X_old, ctx.prec, ctx.n)
+    if pn != po:
+        raise ValueError("X_new and X_old must have the same number of rows")
+    _check(_lib.cum_update(ctx.handle, an, ao, pn), "cum_update")
+
+
+def cum_num_blocks(n: int, b: int, k: int) -> int:
+    return int(_lib.cum_num_blocks(n, b, k))
+
+
+def cum_num_elems(n: int, b: int, k: int) -> int:
+    return int(_lib.cum_num_elems(n, b, k))
+
+
+def cum_get(ctx: Context, k: int, out=None) -> np.ndarray:
+    """Order-k cumulant pyramid (FP64).  ``out`` may be a device tensor."""
+    ne = cum_num_elems(ctx.n, ctx.b, k)
+    if out is None:
+        out = np.empty(ne, dtype=np.float64)
+        _check(_lib.cum_get(ctx.handle, k, out.ctypes.data, ne), "cum_get")
+        return out
+    _check(_lib.cum_get(ctx.handle, k, out.data_ptr(), out.numel()), "cum_get")
+    return out
+
+
+def cum_get_moments(ctx: Context, k: int) -> np.ndarray:
+    ne = cum_num_elems(ctx.n, ctx.b, k)
+    out = np.empty(ne, dtype=np.float64)
+    _check(_lib.cum_get_moments(ctx.handle, k, out.ctypes.data, ne), "cum_get_moments")
+    return out
+
+
+def cum_norms(ctx: Context):
+    """(fro, nu), each of length d+1: fro[k] = ||C_k||_F, nu[k] = Eq. (mef)."""
+    fro = np.empty(ctx.d + 1)
+    nu = np.empty(ctx.d + 1)
+    _check(_lib.cum_norms(ctx.handle, fro.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                          nu.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "cum_norms")
+    return fro, nu
+
+
+def cum_norms_device(ctx: Context) -> int:
+    p = ctypes.c_void_p()
+    _check(_lib.cum_norms_device(ctx.handle, ctypes.byref(p)), "cum_norms_device")
+    return int(p.value)
+
+
+def cum_sync(ctx: Context):
+    _check(_lib.cum_sync(ctx.handle), "cum_sync")
+
+
+def cum_free(ctx: Context):
+    if ctx.handle:
+        _check(_lib.cum_free(ctx.handle), "cum_free")
+        ctx.handle = None
+
+
+def cum_plan_coverage(n: int, b: int, k: int):
+    """Host-only check of the pivot decomposition: (misses, hits-per-element)."""
+    hits = np.zeros(max(cum_num_elems(n, b, k), 1), dtype=np.int32)
+    bad = _lib.cum_plan_coverage(n, b, k, hits.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return int(bad), hits
+
+
+def cum_plan_items(n: int, d: int, b: int) -> int:
+    return int(_lib.cum_plan_items(n, d, b))
