@@ -1,0 +1,191 @@
+"""Sliding-window cumulant update throughput on one MI355X.
+
+Workload: the regime-change stream at n=60 columns, d=4, b=4, window t=20000
+rows, p=1000 rows per update (Gaussian rows first, Gaussian-copula rows with
+Student-t(6)/Exp(1) marginals after step 100).  One step = one cum_update:
+the signed moment contraction of orders 1..4 with its compensated fold, the
+FP64 moment->cumulant combine of every order and the norms / nu_k, all on the
+GPU, with the stream's rows already resident in HBM.
+
+Prints one JSON line: rows/s of the main path (--prec, default fp32) as
+`value`, the per-path figures (fp64, fp32, split-bf16x3) with their sampled
+error against the FP64 oracle, the dominant kernel's roofline, and the
+oracle's own throughput on the host cores (cpu_baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N, D, B, T, P = 60, 4, 4, 20000, 1000
+METRIC = "window updates/s + rows/s at n=60,d=4,b=4; split-BF16 vs FP64 GPU at stated err"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 1e-4}
+
+
+def algorithmic_flops_per_update(p: int) -> float:
+    """One FMA per stored pyramid element per signed row: 2 * (2p) * sum_k E_k."""
+    import paper_1701_06446_amd as cum
+
+    return 2.0 * (2 * p) * sum(cum.cum_num_elems(N, B, k) for k in range(1, D + 1))
+
+
+def sampled_error(ctx, window: np.ndarray, rng, count: int = 40):
+    """Relative error of the GPU cumulants against the per-element FP64 oracle
+    on sampled stored elements of orders 2..d (Frobenius over the sample)."""
+    import paper_1701_06446_amd as cum
+    from oracle.element import cumulant_at, sample_elements
+
+    cache = {}
+    worst = 0.0
+    for k in range(2, D + 1):
+        g = cum.cum_get(ctx, k)
+        offs, idxs = sample_elements(N, B, k, count, rng)
+        ref = np.array([cumulant_at(window, idx, cache) for idx in idxs])
+        err = np.linalg.norm(g[offs] - ref) / max(np.linalg.norm(ref), 1e-300)
+        worst = max(worst, float(err))
+    return worst
+
+
+def run_path(prec, s, warmup, steps, prof_steps, check):
+    import torch
+
+    import paper_1701_06446_amd as cum
+
+    dt = np.float64 if prec == "fp64" else np.float32
+    rows = np.ascontiguousarray(s.rows.astype(dt))
+    dev = torch.from_numpy(rows).to("cuda")
+    ctx = cum.cum_init(N, D, B, dev[:T], prec=prec)
+    w = 0
+
+    def step():
+        nonlocal w
+        w += 1
+        lo, hi = (w - 1) * P, w * P
+        cum.cum_update(ctx, dev[T + lo:T + hi], dev[lo:hi])
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    cum.cum_profile_enable(ctx, True)
+    for _ in range(prof_steps):
+        step()
+    prof = cum.cum_profile_read(ctx)
+    cum.cum_profile_enable(ctx, False)
+    out = {
+        "ms_per_step": elapsed / steps * 1e3,
+        "updates_per_s": steps / elapsed,
+        "rows_per_s": steps * P / elapsed,
+        "kernel_ms": {k: (v[1] / v[0] if v[0] else None) for k, v in prof.items()},
+        "launches_per_step": {k: v[0] / prof_steps for k, v in prof.items()},
+    }
+    if check:
+        window = rows[w * P: w * P + T].astype(np.float64)
+        out["err_sampled"] = sampled_error(ctx, window, np.random.default_rng(7))
+        out["tol"] = TOL[prec]
+    cum.cum_free(ctx)
+    del dev
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(s, budget_s=12.0):
+    """The oracle (as it stands) on the host cores: sliding steps of p=1000 rows
+    at n=60, d=4, b=4 from a 2000-row start window, each step = compensated
+    sums + Alg. 4 combine + Alg. 5 norms."""
+    import oracle
+
+    rows = s.rows.astype(np.float32).astype(np.float64)
+    o = oracle.SlidingOracle(rows[:2000], N, D, B)
+    n_steps, t0 = 0, time.perf_counter()
+    while n_steps < 2 or (time.perf_counter() - t0 < budget_s and n_steps < 30):
+        n_steps += 1
+        lo, hi = (n_steps - 1) * P, n_steps * P
+        o.update(rows[2000 + lo:2000 + hi], rows[lo:hi])
+        oracle.norms(o.cumulants(), N, B)
+    el = time.perf_counter() - t0
+    return {"value": n_steps * P / el, "unit": "rows/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "%d sliding steps of p=1000 rows (n=60,d=4,b=4) from a 2000-row start window; "
+                      "per step: FP64 compensated sums of orders 1..4, Alg.4 combine, Alg.5 norms; "
+                      "%.1f s" % (n_steps, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--paths", default="fp64,fp32,bf16x3", help="precisions to measure")
+    ap.add_argument("--prof-steps", type=int, default=20)
+    ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle check")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import streams
+
+    total_steps = max(200, args.warmup + args.steps + args.prof_steps)
+    s = streams.regime_change_stream(n=N, d=D, b=B, t=T, p=P, steps=total_steps, switch=100)
+    paths = [p for p in args.paths.split(",") if p and p != args.prec] + [args.prec]
+    res = {}
+    for prec in paths:
+        print("[bench] path %s: warmup %d, %d timed steps" % (prec, args.warmup, args.steps),
+              file=sys.stderr, flush=True)
+        res[prec] = run_path(prec, s, args.warmup, args.steps, args.prof_steps, not args.no_check)
+        print("[bench] path %s: %.3f ms/step" % (prec, res[prec]["ms_per_step"]), file=sys.stderr, flush=True)
+    main = res[args.prec]
+    flops = algorithmic_flops_per_update(P)
+    upd_ms = main["kernel_ms"]["update"]
+    achieved = flops / (upd_ms * 1e-3) / 1e12
+    line = {
+        "metric": METRIC,
+        "value": main["rows_per_s"],
+        "unit": "rows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main["ms_per_step"],
+        "updates_per_s": main["updates_per_s"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3 (f32 accumulate)"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": "regime-change stream n=60 d=4 b=4 t=20000 p=1000 (Gaussian, then "
+                               "Gaussian copula with t6/Exp marginals after step 100)",
+                   "n": N, "d": D, "b": B, "t": T, "p": P, "prec": args.prec},
+        "roofline": {"bound": "mfma", "kernel": "k_update", "achieved": achieved,
+                     "peak": PEAK_TFLOPS[args.prec], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_TFLOPS[args.prec],
+                     "flops_per_launch": flops, "kernel_ms": upd_ms, "traffic": None},
+        "paths": res,
+        "device": torch.cuda.get_device_name(0),
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(s)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

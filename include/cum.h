@@ -131,6 +131,21 @@ int cum_norms(cum_ctx *ctx, double *fro, double *nu);
  */
 int cum_norms_device(cum_ctx *ctx, const double **dev_ptr);
 
+/*
+ * cum_profile_enable -- when on != 0, every kernel launch of this context is
+ * bracketed by HIP events on the context's stream (adds a small gap between
+ * launches).  Synchronises and clears earlier records.
+ */
+int cum_profile_enable(cum_ctx *ctx, int on);
+
+/*
+ * cum_profile_read -- per kernel class (0 = moment update, 1 = cumulant
+ * combine, 2 = norms): launches[3] and total_ms[3] of the launches recorded
+ * since profiling was enabled or last read; clears the records.
+ * Synchronises.
+ */
+int cum_profile_read(cum_ctx *ctx, int64_t *launches, double *total_ms);
+
 /* cum_sync -- wait for all work queued on the context's stream. */
 int cum_sync(cum_ctx *ctx);
 

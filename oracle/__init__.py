@@ -56,6 +56,8 @@ def _load():
         lib.orc_block_norm.argtypes = [i32, i32, i32, pd]
         lib.orc_norms.restype = None
         lib.orc_norms.argtypes = [i32, i32, i32, ctypes.POINTER(pd), pd, pd]
+        lib.orc_num_threads.restype = i32
+        lib.orc_num_threads.argtypes = []
         _lib = lib
     return _lib
 
@@ -77,6 +79,11 @@ def tuples(n: int, b: int, k: int) -> np.ndarray:
     out = np.zeros((cnt, k), dtype=np.int32)
     _load().orc_tuples(nbar, k, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
     return out
+
+
+def num_threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return int(_load().orc_num_threads())
 
 
 def count_partitions(s: int, sigma: int) -> int:

@@ -309,3 +309,11 @@ void orc_norms(int n, int b, int d, const double *const *C, double *fro, double 
     else nu[k] = fro[k] / pow(fro[2], 0.5 * k);
   }
 }
+
+/* Threads the OpenMP loops above use. */
+#ifdef _OPENMP
+#include <omp.h>
+int orc_num_threads(void) { return omp_get_max_threads(); }
+#else
+int orc_num_threads(void) { return 1; }
+#endif

@@ -31,7 +31,8 @@ CUM_OK, CUM_EINVAL, CUM_ENOMEM, CUM_EDEVICE, CUM_ESTATE, CUM_ENONFINITE, CUM_ESI
 
 EXPORTS = ("cum_init", "cum_update", "cum_get", "cum_get_moments", "cum_norms",
            "cum_norms_device", "cum_sync", "cum_free", "cum_num_blocks", "cum_num_elems",
-           "cum_strerror", "cum_last_error", "cum_plan_coverage", "cum_plan_items")
+           "cum_strerror", "cum_last_error", "cum_plan_coverage", "cum_plan_items",
+           "cum_profile_enable", "cum_profile_read")
 
 
 class CumError(RuntimeError):
@@ -64,6 +65,8 @@ def _load():
         "cum_last_error": (ctypes.c_char_p, []),
         "cum_plan_coverage": (i64, [i32, i32, i32, ctypes.POINTER(ctypes.c_int32)]),
         "cum_plan_items": (i64, [i32, i32, i32]),
+        "cum_profile_enable": (i32, [vp, i32]),
+        "cum_profile_read": (i32, [vp, ctypes.POINTER(i64), pd]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -200,3 +203,15 @@ def cum_plan_coverage(n: int, b: int, k: int):
 
 def cum_plan_items(n: int, d: int, b: int) -> int:
     return int(_lib.cum_plan_items(n, d, b))
+
+
+def cum_profile_enable(ctx: Context, on: bool = True):
+    _check(_lib.cum_profile_enable(ctx.handle, 1 if on else 0), "cum_profile_enable")
+
+
+def cum_profile_read(ctx: Context):
+    """{"update"|"combine"|"norms": (launches, total_ms)} since the last read."""
+    n = (ctypes.c_int64 * 3)()
+    ms = (ctypes.c_double * 3)()
+    _check(_lib.cum_profile_read(ctx.handle, n, ms), "cum_profile_read")
+    return {name: (int(n[i]), float(ms[i])) for i, name in enumerate(("update", "combine", "norms"))}

@@ -50,6 +50,10 @@ struct cum_ctx {
   void* stage = nullptr;
   size_t stage_bytes = 0;
   std::vector<void*> owned;
+  // optional per-kernel timing: (class, start, stop) per launch
+  bool profiling = false;
+  struct Ev { int cls; hipEvent_t a, b; };
+  std::vector<Ev> events;
 };
 
 namespace {
@@ -117,7 +121,16 @@ bool is_device_ptr(const void* p) {
   return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
 }
 
+void drop_events(cum_ctx* c) {
+  for (auto& e : c->events) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  c->events.clear();
+}
+
 void release(cum_ctx* c) {
+  drop_events(c);
   for (void* p : c->owned) (void)hipFree(p);
   c->owned.clear();
   if (c->stage) (void)hipFree(c->stage);
@@ -139,6 +152,24 @@ int chunk_rows(int prec, int stride) {
   if (r == 0) r = (budget / (stride * ks)) * ks;
   return r;
 }
+
+// Brackets one launch with HIP events when profiling is on (class 0 =
+// update, 1 = combine, 2 = norms).
+struct Timed {
+  cum_ctx* c;
+  int cls;
+  hipEvent_t a = nullptr, b = nullptr;
+  Timed(cum_ctx* ctx, int k) : c(ctx), cls(k) {
+    if (!c->profiling) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
+    (void)hipEventRecord(a, c->stream);
+  }
+  ~Timed() {
+    if (!a) return;
+    (void)hipEventRecord(b, c->stream);
+    c->events.push_back({cls, a, b});
+  }
+};
 
 UpdArgs base_args(cum_ctx* c) {
   UpdArgs a{};
@@ -167,6 +198,7 @@ int run_contraction(cum_ctx* c, const char* xp, int64_t np, const char* xm, int6
     a.xm = cm ? xm + (size_t)q0 * rb : nullptr;
     a.np = (int)cp;
     a.nm = (int)cm;
+    Timed tm(c, 0);
     CUM_TRY(launch_update(c->prec, a, c->nitems, c->stream));
   }
   return CUM_OK;
@@ -187,6 +219,7 @@ int run_combine_and_norms(cum_ctx* c) {
     a.Cout = c->C[s];
     a.mult = c->mult[s];
     a.partial = c->partial[s];
+    Timed tm(c, 1);
     CUM_TRY(launch_combine(c->prec, s, a, c->T.ord[s].nblocks, c->stream));
   }
   NormArgs na{};
@@ -196,6 +229,7 @@ int run_combine_and_norms(cum_ctx* c) {
     na.partial[k] = c->partial[k];
   }
   na.out = c->norms;
+  Timed tm(c, 2);
   CUM_TRY(launch_norms(na, c->stream));
   return CUM_OK;
 }
@@ -429,6 +463,30 @@ int cum_sync(cum_ctx* c) {
   if (!c) return CUM_EINVAL;
   if (!c->ready) return CUM_ESTATE;
   CUM_TRY(hipStreamSynchronize(c->stream));
+  return CUM_OK;
+}
+
+int cum_profile_enable(cum_ctx* c, int on) {
+  if (!c) return CUM_EINVAL;
+  if (!c->ready) return CUM_ESTATE;
+  CUM_TRY(hipStreamSynchronize(c->stream));
+  drop_events(c);
+  c->profiling = on != 0;
+  return CUM_OK;
+}
+
+int cum_profile_read(cum_ctx* c, int64_t* launches, double* total_ms) {
+  if (!c || !launches || !total_ms) return CUM_EINVAL;
+  if (!c->ready) return CUM_ESTATE;
+  CUM_TRY(hipStreamSynchronize(c->stream));
+  for (int q = 0; q < 3; ++q) { launches[q] = 0; total_ms[q] = 0.0; }
+  for (auto& e : c->events) {
+    float ms = 0.f;
+    CUM_TRY(hipEventElapsedTime(&ms, e.a, e.b));
+    launches[e.cls] += 1;
+    total_ms[e.cls] += ms;
+  }
+  drop_events(c);
   return CUM_OK;
 }
 

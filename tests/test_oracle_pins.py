@@ -348,3 +348,20 @@ def test_shift_orthogonal_and_permutation():
     Cp = full_cumulants(X[:, perm], n, d, b)
     for k in range(1, d + 1):
         assert np.allclose(Cp[k - 1], Cb[k - 1][np.ix_(*([perm] * k))], rtol=1e-12, atol=1e-14)
+
+
+def test_element_oracle_matches_pyramid_oracle():
+    """The per-element route (numpy, one multi-index at a time) and the C
+    pyramid oracle agree; the C oracle is pinned above, this pins the sampler
+    used for full-size checks."""
+    from oracle.element import cumulant_at, sample_elements
+
+    n, d, b = 7, 4, 3
+    rng = np.random.default_rng(40)
+    X = rng.exponential(1.0, (500, n)) - 0.5
+    C = oracle.SlidingOracle(X, n, d, b).cumulants()
+    cache = {}
+    for k in range(1, d + 1):
+        offs, idxs = sample_elements(n, b, k, 25, rng)
+        for o, idx in zip(offs, idxs):
+            assert abs(C[k - 1][o] - cumulant_at(X, idx, cache)) <= 1e-12 * (1 + abs(C[k - 1][o]))
