@@ -33,6 +33,7 @@ struct cum_ctx {
   bool ready = false;
   Tables T;
   int nitems = 0;
+  int tm = 2, tn = 2;    // update tile in 16x16 fragments
   int chunk = 0, stride = 0;
   size_t st_size = 0;    // bytes per state element (4 or 8)
   size_t x_size = 0;     // bytes per input element (4 or 8)
@@ -40,11 +41,10 @@ struct cum_ctx {
   void* s_lo[CUM_MAXD + 1] = {};
   double* C[CUM_MAXD + 1] = {};
   double* partial[CUM_MAXD + 1] = {};
-  uint8_t* tuples[CUM_MAXD + 1] = {};
+  int32_t* subrank[CUM_MAXD + 1] = {};
   double* mult[CUM_MAXD + 1] = {};
   LeftCol* left[CUM_MAXD + 1] = {};
   RightCol* right[CUM_MAXD + 1] = {};
-  int64_t* ntab = nullptr;
   UpdItem* items = nullptr;
   double* norms = nullptr;
   void* stage = nullptr;
@@ -142,17 +142,6 @@ int check_shape(int n, int d, int b) {
   return CUM_OK;
 }
 
-// Rows per LDS chunk: a multiple of the MFMA K step (4 or 32 rows), preferably
-// of four steps so that every wave of the workgroup gets the same share.
-int chunk_rows(int prec, int stride) {
-  const int ks = (prec == PREC_BF16X3) ? 32 : 4;
-  const int esz = (prec == PREC_F64) ? 8 : 4;
-  const int budget = UPD_LDS_BYTES / esz;
-  int r = (budget / (stride * 4 * ks)) * 4 * ks;
-  if (r == 0) r = (budget / (stride * ks)) * ks;
-  return r;
-}
-
 // Brackets one launch with HIP events when profiling is on (class 0 =
 // update, 1 = combine, 2 = norms).
 struct Timed {
@@ -171,12 +160,21 @@ struct Timed {
   }
 };
 
+// Update tile shape: CUM_TILE=<TM>x<TN> overrides the default 2x2.
+void pick_tile(cum_ctx* c) {
+  c->tm = 2;
+  c->tn = 2;
+  const char* s = getenv("CUM_TILE");
+  int tm = 0, tn = 0;
+  if (s && sscanf(s, "%dx%d", &tm, &tn) == 2 && update_tile_supported(tm, tn)) {
+    c->tm = tm;
+    c->tn = tn;
+  }
+}
+
 UpdArgs base_args(cum_ctx* c) {
   UpdArgs a{};
   a.n = c->n;
-  a.npad = c->T.npad;
-  a.stride = c->stride;
-  a.chunk = c->chunk;
   a.items = c->items;
   for (int k = 1; k <= c->d; ++k) {
     a.left[k] = c->left[k];
@@ -198,8 +196,9 @@ int run_contraction(cum_ctx* c, const char* xp, int64_t np, const char* xm, int6
     a.xm = cm ? xm + (size_t)q0 * rb : nullptr;
     a.np = (int)cp;
     a.nm = (int)cm;
+    a.vec = ((c->n * c->x_size) % 16 == 0) && ((uintptr_t)a.xp % 16 == 0) && ((uintptr_t)a.xm % 16 == 0);
     Timed tm(c, 0);
-    CUM_TRY(launch_update(c->prec, a, c->nitems, c->stream));
+    CUM_TRY(launch_update(c->prec, c->tm, c->tn, a, c->nitems, c->stream));
   }
   return CUM_OK;
 }
@@ -209,9 +208,9 @@ int run_combine_and_norms(cum_ctx* c) {
     CombArgs a{};
     a.b = c->b;
     a.nbar = c->T.nbar;
+    a.log2b = ((c->b & (c->b - 1)) == 0) ? __builtin_ctz((unsigned)c->b) : -1;
     a.bs = c->T.ord[s].bk;
-    a.tuples = c->tuples[s];
-    a.ntab = c->ntab;
+    a.subrank = c->subrank[s];
     a.s_hi = c->s_hi[s];
     a.s_lo = c->s_lo[s];
     a.inv_t = 1.0 / (double)c->t;
@@ -224,6 +223,7 @@ int run_combine_and_norms(cum_ctx* c) {
   }
   NormArgs na{};
   na.d = c->d;
+  na.kfirst = 1;
   for (int k = 1; k <= c->d; ++k) {
     na.nblocks[k] = c->T.ord[k].nblocks;
     na.partial[k] = c->partial[k];
@@ -292,7 +292,7 @@ int64_t cum_plan_items(int n, int d, int b) {
   if (check_shape(n, d, b) != CUM_OK) return CUM_EINVAL;
   Tables T;
   if (build_tables(n, b, d, T) != 0) return CUM_EINVAL;
-  return (int64_t)build_items(T, 1, d, 16 * UPD_TM, 16 * UPD_TN).size();
+  return (int64_t)build_items(T, 1, d, 32, 32).size();
 }
 
 int cum_init(cum_ctx** out, int n, int d, int b, const void* X, int64_t t, int prec,
@@ -311,10 +311,12 @@ int cum_init(cum_ctx** out, int n, int d, int b, const void* X, int64_t t, int p
   c->x_size = (prec == CUM_FP64) ? 8 : 4;
   c->st_size = (prec == CUM_FP64) ? 8 : 4;
   if (build_tables(n, b, d, c->T) != 0) { delete c; return CUM_EINVAL; }
-  c->stride = c->T.npad + 1;
-  c->chunk = chunk_rows(prec, c->stride);
+  c->stride = update_lds_stride(n);
+  c->chunk = c->stride ? update_chunk_rows(prec, c->stride) : 0;
   if (c->chunk <= 0) { delete c; return CUM_ESIZE; }
-  const std::vector<UpdItem> items = build_items(c->T, 1, d, 16 * UPD_TM, 16 * UPD_TN);
+  pick_tile(c);
+
+  const std::vector<UpdItem> items = build_items(c->T, 1, d, 16 * c->tm, 16 * c->tn);
   c->nitems = (int)items.size();
 
   size_t used = 0;
@@ -333,14 +335,13 @@ int cum_init(cum_ctx** out, int n, int d, int b, const void* X, int64_t t, int p
     if ((e = dalloc(c, &c->s_lo[k], (size_t)o.nelems * c->st_size, &used)) != hipSuccess) return fail(e);
     if ((e = dalloc(c, (void**)&c->C[k], (size_t)o.nelems * 8, &used)) != hipSuccess) return fail(e);
     if ((e = dalloc(c, (void**)&c->partial[k], (size_t)o.nblocks * 8, &used)) != hipSuccess) return fail(e);
-    if ((e = upload(c, &c->tuples[k], c->T.tuples[k], &used)) != hipSuccess) return fail(e);
+    if ((e = upload(c, &c->subrank[k], c->T.subrank[k], &used)) != hipSuccess) return fail(e);
     if ((e = upload(c, &c->mult[k], c->T.mult[k], &used)) != hipSuccess) return fail(e);
     if ((e = upload(c, &c->left[k], c->T.left[k], &used)) != hipSuccess) return fail(e);
     if ((e = upload(c, &c->right[k], c->T.right[k], &used)) != hipSuccess) return fail(e);
     if ((e = hipMemsetAsync(c->s_hi[k], 0, (size_t)o.nelems * c->st_size, c->stream)) != hipSuccess) return fail(e);
     if ((e = hipMemsetAsync(c->s_lo[k], 0, (size_t)o.nelems * c->st_size, c->stream)) != hipSuccess) return fail(e);
   }
-  if ((e = upload(c, &c->ntab, c->T.ntab, &used)) != hipSuccess) return fail(e);
   if ((e = upload(c, &c->items, items, &used)) != hipSuccess) return fail(e);
   if ((e = dalloc(c, (void**)&c->norms, (size_t)2 * (d + 1) * 8, &used)) != hipSuccess) return fail(e);
 

@@ -9,19 +9,17 @@ namespace cum {
 
 enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };
 
-// Update tile: UPD_TM x UPD_TN fragments of 16x16 per workgroup; the four
-// waves of a workgroup split the rows of every LDS chunk between them.
-constexpr int UPD_TM = 2;
-constexpr int UPD_TN = 2;
-constexpr int UPD_LDS_BYTES = 32768;
+// Update tile: TM x TN fragments of 16x16 per workgroup (TM, TN in {2, 4});
+// the four waves of a workgroup split the rows of every LDS chunk between
+// them and are reduced in a fixed order at the end.
+constexpr int UPD_X_BYTES = 32768;     // bytes of data rows per LDS chunk
 
 struct UpdArgs {
   const void* xp;           // rows entering the window (+1), row-major np x n
   const void* xm;           // rows leaving the window (-1), row-major nm x n
   int np, nm;
-  int n, npad;              // data columns, zero-padded columns (nbar*b)
-  int stride;               // LDS row stride in elements (npad + 1)
-  int chunk;                // rows per LDS chunk (multiple of the MFMA K step)
+  int n;                    // data columns (LDS rows hold exactly n values)
+  int vec;                  // 1: rows and both bases allow 16-byte copies
   const UpdItem* items;
   const LeftCol* left[CUM_MAXD + 1];
   const RightCol* right[CUM_MAXD + 1];
@@ -29,11 +27,14 @@ struct UpdArgs {
   void* s_lo[CUM_MAXD + 1];
 };
 
+// LDS budget for a combine block's staged lower-order sub-blocks.
+constexpr size_t COMB_STAGE_BYTES = 65536;
+
 struct CombArgs {
   int b, nbar;
+  int log2b;                // log2(b) when b is a power of two, else -1
   int64_t bs;               // b^s
-  const uint8_t* tuples;    // order-s block tuples
-  const int64_t* ntab;      // N(q, y) table, (CUM_MAXD+1) x (nbar+1)
+  const int32_t* subrank;   // per block and subset mask: rank of the sub-tuple
   const void* s_hi;         // order-s running sums (pair)
   const void* s_lo;
   double inv_t;             // 1/t
@@ -45,12 +46,18 @@ struct CombArgs {
 
 struct NormArgs {
   int d;
+  int kfirst;               // orders below kfirst already hold their norm in out[] (1: none)
   int64_t nblocks[CUM_MAXD + 1];
   const double* partial[CUM_MAXD + 1];
   double* out;              // [0..d] ||C_k||_F, [d+1 .. 2d+1] nu_k
 };
 
-hipError_t launch_update(int prec, const UpdArgs& a, int nitems, hipStream_t st);
+bool update_tile_supported(int tm, int tn);
+// LDS row stride (elements) used for n columns, 0 if n is too large.
+int update_lds_stride(int n);
+// Rows per LDS chunk for a precision and stride (0: not supported).
+int update_chunk_rows(int prec, int str);
+hipError_t launch_update(int prec, int tm, int tn, const UpdArgs& a, int nitems, hipStream_t st);
 hipError_t launch_combine(int prec, int s, const CombArgs& a, int64_t nblocks, hipStream_t st);
 hipError_t launch_norms(const NormArgs& a, hipStream_t st);
 

@@ -10,6 +10,7 @@
 //             the sub-multi-indices, in FP64, one workgroup per stored block.
 //  k_norms    Alg. 5 (exponent 2) and Eq. (mef), deterministic fixed-order sums.
 #include <hip/hip_runtime.h>
+#include <hip/hip_vector_types.h>
 
 #include "cum_internal.h"
 #include "kernels.h"
@@ -64,65 +65,131 @@ __device__ __forceinline__ void fold(T* hi_p, T* lo_p, T d) {
   *lo_p = nl;
 }
 
-// Loads rows [g0, g0 + chunk) of the signed row sequence (plus rows, then
-// minus rows) into LDS, row-major with the given stride; rows past the end
-// are zero.  Padded columns (>= n) were zeroed once and are never written.
-template <typename T>
-__device__ __forceinline__ void load_chunk(T* xs, const UpdArgs& a, int g0) {
-  const T* xp = (const T*)a.xp;
-  const T* xm = (const T*)a.xm;
-  const int K = a.np + a.nm;
-  const int total = a.chunk * a.n;
-  for (int idx = threadIdx.x; idx < total; idx += 256) {
-    const int row = idx / a.n;
-    const int col = idx - row * a.n;
-    const int g = g0 + row;
-    T v = T(0);
-    if (g < a.np) v = xp[(int64_t)g * a.n + col];
-    else if (g < K) v = xm[(int64_t)(g - a.np) * a.n + col];
-    xs[row * a.stride + col] = v;
+// Chunks.  The rows of one contraction are the np rows of xp (sign +1) and
+// the nm rows of xm (sign -1).  They are cut into chunks of R rows that never
+// mix the two signs: ceil(np/R) plus chunks, then ceil(nm/R) minus chunks, the
+// last chunk of each kind zero-filled.  A chunk sits in LDS row-major with a
+// compile-time row stride STR >= n + 4, STR = 4 (mod 32): rows stay 16-byte
+// aligned for 128-bit stores, every k-step offset is an immediate of the LDS
+// read, and four consecutive rows start 4 banks apart.
+template <int P, int STR> struct ChunkGeom {
+  static constexpr int ES = (P == PREC_F64) ? 8 : 4;
+  static constexpr int UB = (P == PREC_BF16X3) ? 128 : 16;     // rows: one k-step for each of 4 waves
+  static constexpr int R = (UPD_X_BYTES / ((STR - 4) * ES)) / UB * UB;  // 0: shape not supported
+};
+
+constexpr int PREF_UNITS = UPD_X_BYTES / 16 / 256;
+
+struct RegChunk {
+  uint4 u[PREF_UNITS];
+};
+
+// Per-thread LDS byte addresses of the 16-byte units it stores (-1: none);
+// the same for every chunk.
+template <int P, int STR>
+__device__ __forceinline__ void chunk_slots(int (&slot)[PREF_UNITS], int n) {
+  using G = ChunkGeom<P, STR>;
+  const int upr = n * G::ES / 16;
+  const int total = G::R * upr;
+  const float inv_upr = 1.0f / (float)upr;
+#pragma unroll
+  for (int q = 0; q < PREF_UNITS; ++q) {
+    const int i = threadIdx.x + 256 * q;
+    // exact for i < 2^20: the fractional part of (i + 0.5)/upr is >= 0.5/upr
+    const int r = (int)(((float)i + 0.5f) * inv_upr);
+    slot[q] = (i < total) ? r * STR * G::ES + (i - r * upr) * 16 : -1;
   }
 }
 
-template <int P, int H, int MR, int TM, int TN>
+// 16-byte units of chunk `ci` into registers (vector path: n*esize % 16 == 0);
+// chunks past the last (ci >= nch) and units past the chunk's rows read zeros.
+template <int P, int STR>
+__device__ __forceinline__ void fetch_chunk(RegChunk& rc, const UpdArgs& a, int ci, int ncp, int nch) {
+  using G = ChunkGeom<P, STR>;
+  const int upr = a.n * G::ES / 16;
+  const bool plus = ci < ncp;
+  const int r0 = (plus ? ci : ci - ncp) * G::R;
+  const int rows = ci < nch ? min(G::R, (plus ? a.np : a.nm) - r0) : 0;
+  const uint4* src = (const uint4*)(plus ? a.xp : a.xm) + (int64_t)r0 * upr + threadIdx.x;
+  const int cnt = rows * upr - (int)threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < PREF_UNITS; ++q)
+    rc.u[q] = (256 * q < cnt) ? src[256 * q] : make_uint4(0u, 0u, 0u, 0u);
+}
+
+template <int P, int STR>
+__device__ __forceinline__ void store_chunk(char* smem, const RegChunk& rc, const int (&slot)[PREF_UNITS]) {
+#pragma unroll
+  for (int q = 0; q < PREF_UNITS; ++q)
+    if (slot[q] >= 0) *(uint4*)(smem + slot[q]) = rc.u[q];
+}
+
+// Scalar path (row length not a multiple of 16 bytes, or unaligned bases).
+template <int P, int STR>
+__device__ __forceinline__ void load_chunk_scalar(char* smem, const UpdArgs& a, int ci, int ncp) {
+  using G = ChunkGeom<P, STR>;
+  using T = typename Tr<P>::X;
+  const bool plus = ci < ncp;
+  const int r0 = (plus ? ci : ci - ncp) * G::R;
+  const int rows = min(G::R, (plus ? a.np : a.nm) - r0);
+  const T* src = (const T*)(plus ? a.xp : a.xm) + (int64_t)r0 * a.n;
+  const int cnt = rows * a.n, total = G::R * a.n;
+  const float inv_n = 1.0f / (float)a.n;
+  T* xs = (T*)smem;
+  for (int i = threadIdx.x; i < total; i += 256) {
+    const int r = (int)(((float)i + 0.5f) * inv_n);
+    xs[r * STR + (i - r * a.n)] = (i < cnt) ? src[i] : T(0);
+  }
+}
+
+// Row mapping inside a chunk of R rows: wave w owns rows [w R/4, (w+1) R/4).
+// f32/f64 (16x16x4): at its k-step s, lane group q = lane/16 takes row
+// w R/4 + 4 s + q.  bf16 (16x16x32): at k-step s, K index 8 q + j of group q
+// is row w R/4 + 32 s + 4 j + q.  A and B use the same row for the same K
+// index, so the products pair up; the four groups always read four
+// consecutive rows (4 banks apart).
+template <int P, int H, int MR, int TM, int TN, int STR, bool VL>
 __device__ void upd_body(const UpdArgs& a, const UpdItem& it, char* smem) {
   using T = typename Tr<P>::X;
   using Acc = typename Tr<P>::Acc;
   using A1 = typename Tr<P>::A1;
+  using G = ChunkGeom<P, STR>;
   constexpr int KS = Tr<P>::KS;
+  constexpr int ES = G::ES;
+  constexpr int R = G::R;
+  constexpr int RW = R / 4;
+  constexpr int NKS = RW / KS;                 // k-steps per wave per chunk
   constexpr int K_ORD = H + MR;
   constexpr int MRC = MR > 0 ? MR : 1;
-  T* xs = (T*)smem;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const LeftCol* __restrict__ left = a.left[K_ORD];
   const RightCol* __restrict__ right = a.right[K_ORD];
+  const int lrow = wave * RW + (lane >> 4);
 
-  // zero the padded columns once
-  for (int idx = tid; idx < a.chunk * (a.npad - a.n); idx += 256) {
-    const int row = idx / (a.npad - a.n);
-    xs[row * a.stride + a.n + (idx - row * (a.npad - a.n))] = T(0);
-  }
-
-  int ac[TM][H];
-  bool av[TM];
-  int bc[TN][MRC];
-  bool bv[TN];
+  // Byte addresses of this lane's factor columns at its first row.  Rows past
+  // M, columns past N and padded data columns read column 0: their products
+  // are computed but never stored, so the inner loop has no masks.
+  int ao[TM][H];
+  int bo[TN][MRC];
 #pragma unroll
   for (int f = 0; f < TM; ++f) {
-    const int r = it.r0 + 16 * f + (lane & 15);
-    av[f] = r < it.M;
-    const LeftCol L = left[it.lrow0 + (av[f] ? r : 0)];
+    const int r = min(it.r0 + 16 * f + (lane & 15), it.M - 1);
+    const LeftCol L = left[it.lrow0 + r];
 #pragma unroll
-    for (int q = 0; q < H; ++q) ac[f][q] = L.c[q];
+    for (int q = 0; q < H; ++q) ao[f][q] = (lrow * STR + (L.c[q] < a.n ? L.c[q] : 0)) * ES;
   }
 #pragma unroll
   for (int g = 0; g < TN; ++g) {
-    const int c = it.c0 + 16 * g + (lane & 15);
-    bv[g] = c < it.N;
-    const RightCol R = right[it.rcol0 + (bv[g] ? c : 0)];
+    const int c = min(it.c0 + 16 * g + (lane & 15), it.N - 1);
+    const RightCol Rc = right[it.rcol0 + c];
 #pragma unroll
-    for (int q = 0; q < MRC; ++q) bc[g][q] = R.c[q];
+    for (int q = 0; q < MRC; ++q) bo[g][q] = (lrow * STR + ((q < MR && Rc.c[q] < a.n) ? Rc.c[q] : 0)) * ES;
   }
+  // (every fragment is multiplied, also those past M or N: branching around
+  // MFMAs makes the compiler shuffle the accumulators through VGPRs)
+  int slot[PREF_UNITS];
+  if constexpr (VL) chunk_slots<P, STR>(slot, a.n);
 
   Acc acc[TM][TN];
 #pragma unroll
@@ -132,71 +199,84 @@ __device__ void upd_body(const UpdArgs& a, const UpdItem& it, char* smem) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[f][g][r] = A1(0);
 
-  const int K = a.np + a.nm;
-  const int nsteps = a.chunk / KS;
-  for (int g0 = 0; g0 < K; g0 += a.chunk) {
+  const int ncp = (a.np + R - 1) / R;
+  const int nch = ncp + (a.nm + R - 1) / R;
+  RegChunk rc;
+  if constexpr (VL) fetch_chunk<P, STR>(rc, a, 0, ncp, nch);
+  for (int ci = 0; ci < nch; ++ci) {
     __syncthreads();
-    load_chunk<T>(xs, a, g0);
-    __syncthreads();
-    for (int ks = wave; ks < nsteps; ks += 4) {
-      if constexpr (KS == 4) {
-        const int row = ks * 4 + (lane >> 4);
-        const T* xr = xs + row * a.stride;
-        const T sgn = (g0 + row < a.np) ? T(1) : T(-1);
+    if constexpr (VL) {
+      store_chunk<P, STR>(smem, rc, slot);
+      __syncthreads();
+      fetch_chunk<P, STR>(rc, a, ci + 1, ncp, nch);
+    } else {
+      load_chunk_scalar<P, STR>(smem, a, ci, ncp);
+      __syncthreads();
+    }
+    // Sign: the minus chunks add their products to the negated accumulators,
+    // acc <- -(-acc + sum_minus) = acc - sum_minus, so no product is negated.
+    if (ci == ncp) {
+#pragma unroll
+      for (int f = 0; f < TM; ++f)
+#pragma unroll
+        for (int g = 0; g < TN; ++g) acc[f][g] = -acc[f][g];
+    }
+    if constexpr (KS == 4) {
+#pragma unroll
+      for (int s = 0; s < NKS; ++s) {
+        const int so = 4 * s * STR * ES;
         T A[TM], B[TN];
 #pragma unroll
         for (int f = 0; f < TM; ++f) {
-          T v = xr[ac[f][0]];
+          T v = *(const T*)(smem + ao[f][0] + so);
 #pragma unroll
-          for (int q = 1; q < H; ++q) v *= xr[ac[f][q]];
-          A[f] = av[f] ? sgn * v : T(0);
+          for (int q = 1; q < H; ++q) v *= *(const T*)(smem + ao[f][q] + so);
+          A[f] = v;
         }
 #pragma unroll
         for (int g = 0; g < TN; ++g) {
           T v = T(1);
           if constexpr (MR > 0) {
-            v = xr[bc[g][0]];
+            v = *(const T*)(smem + bo[g][0] + so);
 #pragma unroll
-            for (int q = 1; q < MR; ++q) v *= xr[bc[g][q]];
+            for (int q = 1; q < MR; ++q) v *= *(const T*)(smem + bo[g][q] + so);
           }
-          B[g] = bv[g] ? v : T(0);
+          B[g] = v;
         }
 #pragma unroll
         for (int f = 0; f < TM; ++f)
 #pragma unroll
           for (int g = 0; g < TN; ++g) acc[f][g] = mma(A[f], B[g], acc[f][g]);
-      } else {
-        // split-BF16x3: v = hi + lo with hi = RNE_bf16(v), lo = RNE_bf16(v - hi);
-        // a*b ~ ah*bh + ah*bl + al*bh, accumulated in FP32.
-        const int rowb = ks * 32 + 8 * (lane >> 4);
+      }
+    } else {
+      // split-BF16x3: v = hi + lo with hi = RNE_bf16(v), lo = RNE_bf16(v - hi);
+      // a*b ~ ah*bh + ah*bl + al*bh, accumulated in FP32.
+#pragma unroll
+      for (int s = 0; s < NKS; ++s) {
         bf16x8 Ah[TM], Al[TM], Bh[TN], Bl[TN];
 #pragma unroll
-        for (int q8 = 0; q8 < 8; ++q8) {
-          const int row = rowb + q8;
-          const float* xr = xs + row * a.stride;
-          const float sgn = (g0 + row < a.np) ? 1.0f : -1.0f;
+        for (int j = 0; j < 8; ++j) {
+          const int so = (32 * s + 4 * j) * STR * ES;
 #pragma unroll
           for (int f = 0; f < TM; ++f) {
-            float v = xr[ac[f][0]];
+            float v = *(const float*)(smem + ao[f][0] + so);
 #pragma unroll
-            for (int q = 1; q < H; ++q) v *= xr[ac[f][q]];
-            v = av[f] ? sgn * v : 0.0f;
+            for (int q = 1; q < H; ++q) v *= *(const float*)(smem + ao[f][q] + so);
             const __bf16 hi = (__bf16)v;
-            Ah[f][q8] = hi;
-            Al[f][q8] = (__bf16)(v - (float)hi);
+            Ah[f][j] = hi;
+            Al[f][j] = (__bf16)(v - (float)hi);
           }
 #pragma unroll
           for (int g = 0; g < TN; ++g) {
             float v = 1.0f;
             if constexpr (MR > 0) {
-              v = xr[bc[g][0]];
+              v = *(const float*)(smem + bo[g][0] + so);
 #pragma unroll
-              for (int q = 1; q < MR; ++q) v *= xr[bc[g][q]];
+              for (int q = 1; q < MR; ++q) v *= *(const float*)(smem + bo[g][q] + so);
             }
-            v = bv[g] ? v : 0.0f;
             const __bf16 hi = (__bf16)v;
-            Bh[g][q8] = hi;
-            Bl[g][q8] = (__bf16)(v - (float)hi);
+            Bh[g][j] = hi;
+            Bl[g][j] = (__bf16)(v - (float)hi);
           }
         }
 #pragma unroll
@@ -211,45 +291,73 @@ __device__ void upd_body(const UpdArgs& a, const UpdItem& it, char* smem) {
     }
   }
 
-  // Reduce the four waves' partial sums in a fixed order, then fold.
-  __syncthreads();
+  if (nch > ncp) {  // undo the negation of the minus phase
+#pragma unroll
+    for (int f = 0; f < TM; ++f)
+#pragma unroll
+      for (int g = 0; g < TN; ++g) acc[f][g] = -acc[f][g];
+  }
+
+  // Reduce the four waves' partial sums in a fixed order (wave 0 + 1 + 2 + 3),
+  // GF fragments at a time through LDS, and fold every stored element.
+  constexpr int NF = TM * TN;
+  constexpr int LDSB = R * STR * ES;
+  constexpr int GMAX = LDSB / (4 * 256 * (int)sizeof(A1));
+  constexpr int GF = NF < GMAX ? NF : GMAX;
+  static_assert(GF >= 1, "reduction buffer");
   A1* red = (A1*)smem;
-  constexpr int FR = TM * TN * 256;
-#pragma unroll
-  for (int f = 0; f < TM; ++f)
-#pragma unroll
-    for (int g = 0; g < TN; ++g)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = frag_row<P>(lane, r), j = lane & 15;
-        red[wave * FR + (f * TN + g) * 256 + i * 16 + j] = acc[f][g][r];
-      }
-  __syncthreads();
   A1* shi = (A1*)a.s_hi[K_ORD];
   A1* slo = (A1*)a.s_lo[K_ORD];
-  for (int e = tid; e < FR; e += 256) {
-    const int fg = e >> 8, i = (e >> 4) & 15, j = e & 15;
-    const int f = fg / TN, g = fg - f * TN;
-    const int r = it.r0 + 16 * f + i, c = it.c0 + 16 * g + j;
-    if (r < it.M && c < it.N) {
-      const A1 sum = ((red[e] + red[FR + e]) + red[2 * FR + e]) + red[3 * FR + e];
-      const int64_t off = left[it.lrow0 + r].base + right[it.rcol0 + c].base;
-      fold<A1>(shi + off, slo + off, sum);
+#pragma unroll
+  for (int f0 = 0; f0 < NF; f0 += GF) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < GF; ++q) {
+      const int fi = f0 + q;
+      if (fi < NF) {
+        const int f = fi / TN, g = fi % TN;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          red[(wave * GF + q) * 256 + frag_row<P>(lane, r) * 16 + (lane & 15)] = acc[f][g][r];
+      }
+    }
+    __syncthreads();
+    const int cnt = (NF - f0 < GF ? NF - f0 : GF) * 256;
+    for (int e = tid; e < cnt; e += 256) {
+      const int fi = f0 + (e >> 8), i = (e >> 4) & 15, j = e & 15;
+      const int f = fi / TN, g = fi - f * TN;
+      const int r = it.r0 + 16 * f + i, c = it.c0 + 16 * g + j;
+      if (r < it.M && c < it.N) {
+        const LeftCol L = left[it.lrow0 + r];
+        const RightCol Rc = right[it.rcol0 + c];
+        bool pad = false;
+#pragma unroll
+        for (int q = 0; q < H; ++q) pad = pad || L.c[q] >= a.n;
+#pragma unroll
+        for (int q = 0; q < MR; ++q) pad = pad || Rc.c[q] >= a.n;
+        if (!pad) {
+          const A1 sum = ((red[e] + red[GF * 256 + e]) + red[2 * GF * 256 + e]) + red[3 * GF * 256 + e];
+          const int64_t off = L.base + Rc.base;
+          fold<A1>(shi + off, slo + off, sum);
+        }
+      }
     }
   }
 }
 
-template <int P, int TM, int TN>
+template <int P, int TM, int TN, int STR, bool VL>
 __global__ __launch_bounds__(256) void k_update(UpdArgs a) {
-  __shared__ __attribute__((aligned(16))) char smem[UPD_LDS_BYTES];
+  using G = ChunkGeom<P, STR>;
+  static_assert(G::R >= G::UB, "chunk smaller than one unit block per wave");
+  __shared__ __attribute__((aligned(16))) char smem[G::R * STR * G::ES];
   const UpdItem it = a.items[blockIdx.x];
   switch (it.k) {
-    case 1: upd_body<P, 1, 0, TM, TN>(a, it, smem); break;
-    case 2: upd_body<P, 1, 1, TM, TN>(a, it, smem); break;
-    case 3: upd_body<P, 2, 1, TM, TN>(a, it, smem); break;
-    case 4: upd_body<P, 2, 2, TM, TN>(a, it, smem); break;
-    case 5: upd_body<P, 3, 2, TM, TN>(a, it, smem); break;
-    case 6: upd_body<P, 3, 3, TM, TN>(a, it, smem); break;
+    case 1: upd_body<P, 1, 0, TM, TN, STR, VL>(a, it, smem); break;
+    case 2: upd_body<P, 1, 1, TM, TN, STR, VL>(a, it, smem); break;
+    case 3: upd_body<P, 2, 1, TM, TN, STR, VL>(a, it, smem); break;
+    case 4: upd_body<P, 2, 2, TM, TN, STR, VL>(a, it, smem); break;
+    case 5: upd_body<P, 3, 2, TM, TN, STR, VL>(a, it, smem); break;
+    case 6: upd_body<P, 3, 3, TM, TN, STR, VL>(a, it, smem); break;
     default: break;
   }
 }
@@ -301,72 +409,105 @@ template <int S> constexpr PartTable<S> make_parts() {
 
 template <int S> __device__ constexpr PartTable<S> kParts = make_parts<S>();
 
-// Lexicographic rank of a non-decreasing m-tuple among all such tuples over
-// [0, nbar): sum_i N(m-i+1, j_{i-1}) - N(m-i+1, j_i) with j_0 = 0, where
-// N(q, y) counts the sorted q-tuples over [y, nbar).
-__device__ __forceinline__ int64_t tuple_rank(const int* j, int m, const int64_t* ntab, int nbar) {
-  int64_t r = 0;
-  int prev = 0;
-  for (int i = 0; i < m; ++i) {
-    const int q = m - i;
-    r += ntab[q * (nbar + 1) + prev] - ntab[q * (nbar + 1) + j[i]];
-    prev = j[i];
+// Partition sum of Alg. 4 for one element: the sum, over every partition of
+// {1..S} into 2..S parts, of the product of the lower-order cumulants c_B.
+template <int S>
+__device__ __forceinline__ double partition_sum(const double (&cB)[1 << S]) {
+  double A = 0.0;
+#pragma unroll
+  for (int p = 0; p < kParts<S>.count; ++p) {
+    double prod = cB[kParts<S>.mask[p][0]];
+#pragma unroll
+    for (int q = 1; q < S; ++q)
+      if (q < kParts<S>.nparts[p]) prod *= cB[kParts<S>.mask[p][q]];
+    A += prod;
   }
-  return r;
+  return A;
 }
 
-template <int S, typename St>
+// One workgroup per stored block of order S.  The lower-order cumulant
+// sub-blocks C_|B|(j_B) of the block (every non-empty proper subset B of the
+// S positions) are staged in LDS when they fit (STAGE), else gathered from
+// global memory.  Each element is c = S_s/t - (sum over partitions of
+// {1..S} into 2..S parts of prod_B c_B), Alg. 3/4.  The block's weighted
+// sum of squares (Alg. 5) goes to partial[blk].
+template <int S, typename St, bool STAGE>
 __global__ __launch_bounds__(256) void k_combine(CombArgs a) {
   constexpr int NM = 1 << S;
   constexpr int FULL = NM - 1;
+  extern __shared__ __attribute__((aligned(16))) double stage[];
   __shared__ int64_t subbase[NM];
+  __shared__ int lds_off[NM + 1];
   __shared__ double red[256];
   const int tid = threadIdx.x;
   const int64_t blk = blockIdx.x;
   const int b = a.b;
-
-  if (tid > 0 && tid < FULL) {
-    int j[CUM_MAXD], len = 0;
-    for (int q = 0; q < S; ++q)
-      if (tid & (1 << q)) j[len++] = a.tuples[blk * S + q];
-    int64_t bl = 1;
-    for (int q = 0; q < len; ++q) bl *= b;
-    subbase[tid] = tuple_rank(j, len, a.ntab, a.nbar) * bl;
-  }
-  __syncthreads();
-
   const St* shi = (const St*)a.s_hi;
   const St* slo = (const St*)a.s_lo;
+
+  // the first element's running sums are independent of the prologue
+  const int64_t o0 = blk * a.bs + tid;
+  const double m0 = tid < a.bs ? ((double)shi[o0] + (double)slo[o0]) * a.inv_t : 0.0;
+
+  if (tid == 0) {
+    // LDS offsets of the staged sub-blocks, in mask order
+    int off = 0;
+    for (int mask = 1; mask < FULL; ++mask) {
+      int bl = 1;
+      for (int q = 0; q < __builtin_popcount(mask); ++q) bl *= b;
+      lds_off[mask] = off;
+      off += bl;
+    }
+    lds_off[FULL] = off;
+  }
+  if (tid > 0 && tid < FULL) {
+    int64_t bl = 1;
+    for (int q = 0; q < __builtin_popcount(tid); ++q) bl *= b;
+    subbase[tid] = (int64_t)a.subrank[blk * NM + tid] * bl;
+  }
+  __syncthreads();
+  if constexpr (STAGE) {
+    const int total = lds_off[FULL];
+    for (int i = tid; i < total; i += 256) {
+      int mask = 1;
+      while (mask + 1 < FULL && lds_off[mask + 1] <= i) ++mask;
+      stage[i] = a.C[__builtin_popcount(mask)][subbase[mask] + (i - lds_off[mask])];
+    }
+    __syncthreads();
+  }
+
   double sq = 0.0;
+  const int lb = a.log2b;  // >= 0 when b is a power of two
   for (int64_t e = tid; e < a.bs; e += 256) {
     int dig[S];
-    int64_t rem = e;
+    if (lb >= 0) {
+      const int mb = b - 1;
 #pragma unroll
-    for (int q = S - 1; q >= 0; --q) {
-      dig[q] = (int)(rem % b);
-      rem /= b;
+      for (int q = S - 1; q >= 0; --q) dig[q] = (int)(e >> (lb * (S - 1 - q))) & mb;
+    } else {
+      int64_t rem = e;
+#pragma unroll
+      for (int q = S - 1; q >= 0; --q) {
+        dig[q] = (int)(rem % b);
+        rem /= b;
+      }
     }
     double cB[NM];
 #pragma unroll
     for (int mask = 1; mask < FULL; ++mask) {
-      int64_t off = 0;
-      int len = 0;
+      int off = 0;
 #pragma unroll
       for (int q = 0; q < S; ++q)
-        if (mask & (1 << q)) { off = off * b + dig[q]; ++len; }
-      cB[mask] = a.C[len][subbase[mask] + off];
+        if (mask & (1 << q)) off = off * b + dig[q];
+      if constexpr (STAGE) {
+        cB[mask] = stage[lds_off[mask] + off];
+      } else {
+        cB[mask] = a.C[__builtin_popcount(mask)][subbase[mask] + off];
+      }
     }
-    double A = 0.0;
-#pragma unroll
-    for (int p = 0; p < kParts<S>.count; ++p) {
-      double prod = cB[kParts<S>.mask[p][0]];
-#pragma unroll
-      for (int q = 1; q < S; ++q)
-        if (q < kParts<S>.nparts[p]) prod *= cB[kParts<S>.mask[p][q]];
-      A += prod;
-    }
+    const double A = partition_sum<S>(cB);
     const int64_t o = blk * a.bs + e;
-    const double mval = ((double)shi[o] + (double)slo[o]) * a.inv_t;
+    const double mval = (e == tid) ? m0 : ((double)shi[o] + (double)slo[o]) * a.inv_t;
     const double c = mval - A;
     a.Cout[o] = c;
     sq += c * c;
@@ -380,62 +521,132 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a) {
   if (tid == 0) a.partial[blk] = a.mult[blk] * red[0];
 }
 
-// Final norms: fro[k] = sqrt(sum of the order's block partials), summed in a
-// fixed order; nu[k] = fro[k] / fro[2]^(k/2) for k >= 3 (Eq. (mef)).
-__global__ __launch_bounds__(256) void k_norms(NormArgs a) {
-  __shared__ double red[256];
+// Final norms (Alg. 5 with exponent 2, Eq. (mef)): fro[k] = sqrt(sum of the
+// order's block partials), each order summed by a fixed thread/tree order;
+// nu[k] = fro[k] / fro[2]^(k/2) for k >= 3.  One workgroup of 1024 threads;
+// every thread issues its loads before summing, so an order costs about one
+// memory round trip.
+__global__ __launch_bounds__(1024) void k_norms(NormArgs a) {
+  __shared__ double red[1024];
+  __shared__ double fro[CUM_MAXD + 1];
   const int tid = threadIdx.x;
-  for (int k = 1; k <= a.d; ++k) {
-    double s = 0.0;
-    for (int64_t i = tid; i < a.nblocks[k]; i += 256) s += a.partial[k][i];
+  if (tid < a.kfirst) fro[tid] = a.out[tid];  // written by the small-order kernel
+  for (int k = a.kfirst; k <= a.d; ++k) {
+    const double* p = a.partial[k];
+    const int64_t nb = a.nblocks[k];
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t i = tid + 1024 * u;
+      v[u] = i < nb ? p[i] : 0.0;
+    }
+    double s = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+    for (int64_t i = tid + 8192; i < nb; i += 1024) s += p[i];
     red[tid] = s;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = 512; w > 0; w >>= 1) {
       if (tid < w) red[tid] += red[tid + w];
       __syncthreads();
     }
-    if (tid == 0) a.out[k] = sqrt(red[0]);
+    if (tid == 0) fro[k] = sqrt(red[0]);
     __syncthreads();
   }
-  if (tid == 0) {
-    a.out[0] = __builtin_nan("");
-    for (int k = 0; k <= a.d; ++k)
-      a.out[a.d + 1 + k] = (k >= 3) ? a.out[k] / pow(a.out[2], 0.5 * k) : __builtin_nan("");
+  if (tid <= a.d) {
+    a.out[tid] = tid == 0 ? __builtin_nan("") : fro[tid];
+    a.out[a.d + 1 + tid] = (tid >= 3) ? fro[tid] / pow(fro[2], 0.5 * tid) : __builtin_nan("");
   }
 }
 
 // ---------------------------------------------------------------------------
 // Launch wrappers.
 
-template <int P>
-static hipError_t launch_update_p(const UpdArgs& a, int nitems, hipStream_t st) {
-  hipLaunchKernelGGL((k_update<P, UPD_TM, UPD_TN>), dim3(nitems), dim3(256), 0, st, a);
-  return hipGetLastError();
+template <int P, int TM, int TN, int STR>
+static hipError_t launch_one(const UpdArgs& a, int nitems, hipStream_t st) {
+  if constexpr (ChunkGeom<P, STR>::R >= ChunkGeom<P, STR>::UB) {
+    if (a.vec) hipLaunchKernelGGL((k_update<P, TM, TN, STR, true>), dim3(nitems), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_update<P, TM, TN, STR, false>), dim3(nitems), dim3(256), 0, st, a);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
 }
 
-hipError_t launch_update(int prec, const UpdArgs& a, int nitems, hipStream_t st) {
-  if (nitems <= 0) return hipSuccess;
-  switch (prec) {
-    case PREC_F64: return launch_update_p<PREC_F64>(a, nitems, st);
-    case PREC_F32: return launch_update_p<PREC_F32>(a, nitems, st);
-    case PREC_BF16X3: return launch_update_p<PREC_BF16X3>(a, nitems, st);
+template <int P, int TM, int TN>
+static hipError_t launch_update_s(int str, const UpdArgs& a, int nitems, hipStream_t st) {
+  switch (str) {
+    case 36: return launch_one<P, TM, TN, 36>(a, nitems, st);
+    case 68: return launch_one<P, TM, TN, 68>(a, nitems, st);
+    case 132: return launch_one<P, TM, TN, 132>(a, nitems, st);
+    case 260: return launch_one<P, TM, TN, 260>(a, nitems, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <int P>
+static hipError_t launch_update_p(int tm, int tn, int str, const UpdArgs& a, int nitems, hipStream_t st) {
+  if (tm == 2 && tn == 2) return launch_update_s<P, 2, 2>(str, a, nitems, st);
+  if (tm == 4 && tn == 4) return launch_update_s<P, 4, 4>(str, a, nitems, st);
+  return hipErrorInvalidValue;
+}
+
+bool update_tile_supported(int tm, int tn) {
+  return (tm == 2 && tn == 2) || (tm == 4 && tn == 4);
+}
+
+int update_lds_stride(int n) {
+  return n <= 32 ? 36 : n <= 64 ? 68 : n <= 128 ? 132 : n <= 256 ? 260 : 0;
+}
+
+// 0 when the precision cannot use this stride (bf16x3 needs 128-row chunks).
+int update_chunk_rows(int prec, int str) {
+  switch (prec) {
+    case PREC_F64:
+      return str == 36 ? ChunkGeom<PREC_F64, 36>::R : str == 68 ? ChunkGeom<PREC_F64, 68>::R
+           : str == 132 ? ChunkGeom<PREC_F64, 132>::R : ChunkGeom<PREC_F64, 260>::R;
+    case PREC_F32:
+      return str == 36 ? ChunkGeom<PREC_F32, 36>::R : str == 68 ? ChunkGeom<PREC_F32, 68>::R
+           : str == 132 ? ChunkGeom<PREC_F32, 132>::R : ChunkGeom<PREC_F32, 260>::R;
+    default:
+      return str == 36 ? ChunkGeom<PREC_BF16X3, 36>::R : str == 68 ? ChunkGeom<PREC_BF16X3, 68>::R
+           : str == 132 ? ChunkGeom<PREC_BF16X3, 132>::R : ChunkGeom<PREC_BF16X3, 260>::R;
+  }
+}
+
+hipError_t launch_update(int prec, int tm, int tn, const UpdArgs& a, int nitems, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  const int str = update_lds_stride(a.n);
+  switch (prec) {
+    case PREC_F64: return launch_update_p<PREC_F64>(tm, tn, str, a, nitems, st);
+    case PREC_F32: return launch_update_p<PREC_F32>(tm, tn, str, a, nitems, st);
+    case PREC_BF16X3: return launch_update_p<PREC_BF16X3>(tm, tn, str, a, nitems, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int S, typename St>
+static hipError_t launch_combine_s(const CombArgs& a, int64_t nblocks, hipStream_t st) {
+  const dim3 grid((unsigned)nblocks), blk(256);
+  // staged sub-blocks: (b+1)^S - 1 - b^S doubles
+  int64_t tot = 1, bs = 1;
+  for (int q = 0; q < S; ++q) { tot *= (a.b + 1); bs *= a.b; }
+  tot = tot - 1 - bs;
+  const size_t bytes = (size_t)tot * sizeof(double);
+  if (bytes <= COMB_STAGE_BYTES) hipLaunchKernelGGL((k_combine<S, St, true>), grid, blk, bytes, st, a);
+  else hipLaunchKernelGGL((k_combine<S, St, false>), grid, blk, 0, st, a);
+  return hipGetLastError();
 }
 
 template <typename St>
 static hipError_t launch_combine_t(int s, const CombArgs& a, int64_t nblocks, hipStream_t st) {
-  const dim3 grid((unsigned)nblocks), blk(256);
   switch (s) {
-    case 1: hipLaunchKernelGGL((k_combine<1, St>), grid, blk, 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_combine<2, St>), grid, blk, 0, st, a); break;
-    case 3: hipLaunchKernelGGL((k_combine<3, St>), grid, blk, 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_combine<4, St>), grid, blk, 0, st, a); break;
-    case 5: hipLaunchKernelGGL((k_combine<5, St>), grid, blk, 0, st, a); break;
-    case 6: hipLaunchKernelGGL((k_combine<6, St>), grid, blk, 0, st, a); break;
+    case 1: return launch_combine_s<1, St>(a, nblocks, st);
+    case 2: return launch_combine_s<2, St>(a, nblocks, st);
+    case 3: return launch_combine_s<3, St>(a, nblocks, st);
+    case 4: return launch_combine_s<4, St>(a, nblocks, st);
+    case 5: return launch_combine_s<5, St>(a, nblocks, st);
+    case 6: return launch_combine_s<6, St>(a, nblocks, st);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_combine(int prec, int s, const CombArgs& a, int64_t nblocks, hipStream_t st) {
@@ -445,8 +656,9 @@ hipError_t launch_combine(int prec, int s, const CombArgs& a, int64_t nblocks, h
 }
 
 hipError_t launch_norms(const NormArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_norms, dim3(1), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_norms, dim3(1), dim3(1024), 0, st, a);
   return hipGetLastError();
 }
+
 
 }  // namespace cum

@@ -56,12 +56,6 @@ int build_tables(int n, int b, int d, Tables& T) {
   if (T.nbar > 255 || T.npad > 65535) return -1;
   const int nbar = T.nbar;
 
-  // N(m, y) = number of sorted m-tuples over [y, nbar) = C(nbar - y + m - 1, m)
-  T.ntab.assign((size_t)(CUM_MAXD + 1) * (nbar + 1), 0);
-  for (int m = 0; m <= CUM_MAXD; ++m)
-    for (int y = 0; y <= nbar; ++y)
-      T.ntab[(size_t)m * (nbar + 1) + y] = (m == 0) ? 1 : binom(nbar - y + m - 1, m);
-
   std::unordered_map<uint64_t, int64_t> rank;
   for (int k = 1; k <= d; ++k) {
     OrderInfo& o = T.ord[k];
@@ -88,6 +82,24 @@ int build_tables(int n, int b, int d, Tables& T) {
         run = 1;
       }
       T.mult[k][(size_t)r] = kf / den;
+    }
+  }
+
+  // Sub-block ranks for the combine: every proper non-empty subset of the
+  // positions of every stored block.
+  for (int k = 1; k <= d; ++k) {
+    const int nm = 1 << k;
+    const int64_t nb = T.ord[k].nblocks;
+    T.subrank[k].assign((size_t)nb * nm, 0);
+    for (int64_t r = 0; r < nb; ++r) {
+      for (int mask = 1; mask < nm - 1; ++mask) {
+        int j[CUM_MAXD], len = 0;
+        for (int q = 0; q < k; ++q)
+          if (mask & (1 << q)) j[len++] = T.tuples[k][(size_t)r * k + q];
+        auto it = rank.find(key_of(j, len));
+        if (it == rank.end()) return -4;
+        T.subrank[k][(size_t)r * nm + mask] = (int32_t)it->second;
+      }
     }
   }
 

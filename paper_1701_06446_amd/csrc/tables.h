@@ -20,7 +20,9 @@ struct Tables {
   OrderInfo ord[CUM_MAXD + 1] = {};
   std::vector<uint8_t> tuples[CUM_MAXD + 1];   // order-k block tuples, k bytes each
   std::vector<double> mult[CUM_MAXD + 1];      // k!/prod(r_l!) per block
-  std::vector<int64_t> ntab;                   // N(m, y), (CUM_MAXD+1) x (nbar+1)
+  // subrank[s][blk * 2^s + mask]: rank, among the sorted |B|-tuples, of the
+  // block tuple restricted to the positions in mask (proper, non-empty B)
+  std::vector<int32_t> subrank[CUM_MAXD + 1];
   std::vector<LeftCol> left[CUM_MAXD + 1];
   std::vector<RightCol> right[CUM_MAXD + 1];
   std::vector<Pivot> piv[CUM_MAXD + 1];
