@@ -119,7 +119,7 @@ class Context:
         self.handle, self.n, self.d, self.b, self.t, self.prec = handle, n, d, b, t, prec
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.cum_free(self.handle)
             self.handle = None
 
