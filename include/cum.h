@@ -166,6 +166,27 @@ const char *cum_strerror(int status);
 const char *cum_last_error(void);
 
 /*
+ * Batched streams.  cum_batch_create groups m initialised contexts (same
+ * precision, any n, d, b, t; each at most one batch) and captures one HIP
+ * graph that updates all of them: persistent update launches over the
+ * tiles of every member (longest windows first), the combine of every order
+ * for every member, and every member's norms.  The batch runs on a stream of
+ * its own; member contexts wait for it before cum_get / cum_norms /
+ * cum_update.  Free the batch before its members.
+ *
+ * cum_batch_update(bt, X_new[m], X_old[m], p[m]) slides member i by p[i]
+ * rows (0 <= p[i] <= min(t_i, 2048)); every pointer must be device memory
+ * (16-byte aligned when n*sizeof(element) is a multiple of 16) and stay
+ * unchanged until the work completes (cum_batch_sync).  CUM_EINVAL on any
+ * violation, before any work is queued.
+ */
+typedef struct cum_batch cum_batch;
+int cum_batch_create(cum_batch **batch, cum_ctx *const *ctxs, int m);
+int cum_batch_update(cum_batch *batch, const void *const *X_new, const void *const *X_old, const int64_t *p);
+int cum_batch_sync(cum_batch *batch);
+int cum_batch_free(cum_batch *batch);
+
+/*
  * cum_plan_coverage -- host-only check of the update's pivot decomposition
  * (no GPU needed): for order k, counts how many (pivot, row, column)
  * products of the update land on each stored element (written to `hits`,

@@ -32,7 +32,8 @@ CUM_OK, CUM_EINVAL, CUM_ENOMEM, CUM_EDEVICE, CUM_ESTATE, CUM_ENONFINITE, CUM_ESI
 EXPORTS = ("cum_init", "cum_update", "cum_get", "cum_get_moments", "cum_norms",
            "cum_norms_device", "cum_sync", "cum_free", "cum_num_blocks", "cum_num_elems",
            "cum_strerror", "cum_last_error", "cum_plan_coverage", "cum_plan_items",
-           "cum_profile_enable", "cum_profile_read")
+           "cum_profile_enable", "cum_profile_read", "cum_batch_create", "cum_batch_update",
+           "cum_batch_sync", "cum_batch_free")
 
 
 class CumError(RuntimeError):
@@ -66,6 +67,10 @@ def _load():
         "cum_plan_coverage": (i64, [i32, i32, i32, ctypes.POINTER(ctypes.c_int32)]),
         "cum_plan_items": (i64, [i32, i32, i32]),
         "cum_profile_enable": (i32, [vp, i32]),
+        "cum_batch_create": (i32, [ctypes.POINTER(vp), ctypes.POINTER(vp), i32]),
+        "cum_batch_update": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64)]),
+        "cum_batch_sync": (i32, [vp]),
+        "cum_batch_free": (i32, [vp]),
         "cum_profile_read": (i32, [vp, ctypes.POINTER(i64), pd]),
     }
     for name, (res, args) in sig.items():
@@ -215,3 +220,51 @@ def cum_profile_read(ctx: Context):
     ms = (ctypes.c_double * 3)()
     _check(_lib.cum_profile_read(ctx.handle, n, ms), "cum_profile_read")
     return {name: (int(n[i]), float(ms[i])) for i, name in enumerate(("update", "combine", "norms"))}
+
+
+class Batch:
+    """Owns one ``cum_batch`` over member contexts (kept alive here)."""
+
+    def __init__(self, handle, ctxs):
+        self.handle, self.ctxs = handle, list(ctxs)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.cum_batch_free(self.handle)
+            self.handle = None
+
+
+def cum_batch_create(ctxs) -> Batch:
+    """One captured graph that updates every context in ``ctxs``."""
+    arr = (ctypes.c_void_p * len(ctxs))(*[c.handle for c in ctxs])
+    h = ctypes.c_void_p()
+    _check(_lib.cum_batch_create(ctypes.byref(h), arr, len(ctxs)), "cum_batch_create")
+    return Batch(h, ctxs)
+
+
+def cum_batch_update(batch: Batch, X_new, X_old):
+    """Slide member i by len(X_new[i]) rows; device tensors only."""
+    m = len(batch.ctxs)
+    assert len(X_new) == m and len(X_old) == m
+    pn = (ctypes.c_void_p * m)()
+    po = (ctypes.c_void_p * m)()
+    pp = (ctypes.c_int64 * m)()
+    keep = []
+    for i, c in enumerate(batch.ctxs):
+        an, rn, k1 = _pointer(X_new[i], c.prec, c.n)
+        ao, ro, k2 = _pointer(X_old[i], c.prec, c.n)
+        if rn != ro:
+            raise ValueError("X_new and X_old must have the same number of rows")
+        pn[i], po[i], pp[i] = an, ao, rn
+        keep += [k1, k2]
+    _check(_lib.cum_batch_update(batch.handle, pn, po, pp), "cum_batch_update")
+
+
+def cum_batch_sync(batch: Batch):
+    _check(_lib.cum_batch_sync(batch.handle), "cum_batch_sync")
+
+
+def cum_batch_free(batch: Batch):
+    if batch.handle:
+        _check(_lib.cum_batch_free(batch.handle), "cum_batch_free")
+        batch.handle = None

@@ -11,6 +11,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -50,6 +51,10 @@ struct cum_ctx {
   void* stage = nullptr;
   size_t stage_bytes = 0;
   std::vector<void*> owned;
+  // set while this context belongs to a batch: the batch's last step, and
+  // whether the context was updated directly since (the batch then waits)
+  hipEvent_t batch_done = nullptr;
+  bool direct_since_batch = false;
   // optional per-kernel timing: (class, start, stop) per launch
   bool profiling = false;
   struct Ev { int cls; hipEvent_t a, b; };
@@ -234,6 +239,13 @@ int run_combine_and_norms(cum_ctx* c) {
   return CUM_OK;
 }
 
+// Work of a batch that contains this context must finish before its state
+// is read on the host.
+hipError_t wait_batch(cum_ctx* c) {
+  if (!c->batch_done) return hipSuccess;
+  return hipEventSynchronize(c->batch_done);
+}
+
 int ensure_stage(cum_ctx* c, size_t bytes) {
   if (bytes <= c->stage_bytes) return CUM_OK;
   CUM_TRY(hipStreamSynchronize(c->stream));
@@ -401,6 +413,10 @@ int cum_update(cum_ctx* c, const void* X_new, const void* X_old, int64_t p) {
     // host buffers are free for reuse once this returns
     CUM_TRY(hipStreamSynchronize(c->stream));
   }
+  if (c->batch_done) {
+    CUM_TRY(hipStreamWaitEvent(c->stream, c->batch_done, 0));
+    c->direct_since_batch = true;
+  }
   int rc = run_contraction(c, xn, p, xo, p);
   if (rc != CUM_OK) return rc;
   return run_combine_and_norms(c);
@@ -412,6 +428,7 @@ int cum_get(cum_ctx* c, int k, double* blocks, size_t capacity_elems) {
   if (k < 1 || k > c->d || !blocks) return CUM_EINVAL;
   const size_t ne = (size_t)c->T.ord[k].nelems;
   if (capacity_elems < ne) return CUM_ESIZE;
+  CUM_TRY(wait_batch(c));
   CUM_TRY(hipStreamSynchronize(c->stream));
   CUM_TRY(hipMemcpy(blocks, c->C[k], ne * 8, hipMemcpyDefault));
   return CUM_OK;
@@ -423,6 +440,7 @@ int cum_get_moments(cum_ctx* c, int k, double* blocks, size_t capacity_elems) {
   if (k < 1 || k > c->d || !blocks) return CUM_EINVAL;
   const size_t ne = (size_t)c->T.ord[k].nelems;
   if (capacity_elems < ne) return CUM_ESIZE;
+  CUM_TRY(wait_batch(c));
   CUM_TRY(hipStreamSynchronize(c->stream));
   std::vector<char> hi(ne * c->st_size), lo(ne * c->st_size);
   std::vector<double> m(ne);
@@ -443,6 +461,7 @@ int cum_norms(cum_ctx* c, double* fro, double* nu) {
   if (!c) return CUM_EINVAL;
   if (!c->ready) return CUM_ESTATE;
   if (!fro || !nu) return CUM_EINVAL;
+  CUM_TRY(wait_batch(c));
   CUM_TRY(hipStreamSynchronize(c->stream));
   std::vector<double> h((size_t)2 * (c->d + 1));
   CUM_TRY(hipMemcpy(h.data(), c->norms, h.size() * 8, hipMemcpyDeviceToHost));
@@ -463,6 +482,7 @@ int cum_norms_device(cum_ctx* c, const double** dev_ptr) {
 int cum_sync(cum_ctx* c) {
   if (!c) return CUM_EINVAL;
   if (!c->ready) return CUM_ESTATE;
+  CUM_TRY(wait_batch(c));
   CUM_TRY(hipStreamSynchronize(c->stream));
   return CUM_OK;
 }
@@ -493,9 +513,258 @@ int cum_profile_read(cum_ctx* c, int64_t* launches, double* total_ms) {
 
 int cum_free(cum_ctx* c) {
   if (!c) return CUM_OK;
+  if (c->ready) (void)wait_batch(c);
   if (c->ready) (void)hipStreamSynchronize(c->stream);
   release(c);
   delete c;
+  return CUM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched streams: one graph per batch replays the update of every member
+// context (persistent launches grouped by LDS stride, batched combine per
+// order, batched norms).  Only the input pointers and row counts change
+// between updates; they are copied into the device argument table first.
+
+struct cum_batch {
+  std::vector<cum_ctx*> ctx;
+  int prec = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<UpdArgs> h_upd;
+  UpdArgs* d_upd = nullptr;
+  struct Group { int str; bool vl; UpdItem* items; int nitems; int grid; };
+  std::vector<Group> groups;
+  CombArgs* d_comb[CUM_MAXD + 1] = {};
+  int64_t* comb_items[CUM_MAXD + 1] = {};
+  int ncomb[CUM_MAXD + 1] = {};
+  int comb_grid[CUM_MAXD + 1] = {};
+  size_t stage_bytes[CUM_MAXD + 1] = {};
+  NormArgs* d_norm = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;
+  std::vector<void*> owned;
+};
+
+namespace {
+
+void batch_release(cum_batch* bt) {
+  if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+  if (bt->graph) (void)hipGraphDestroy(bt->graph);
+  for (cum_ctx* c : bt->ctx)
+    if (c && c->batch_done == bt->done) c->batch_done = nullptr;
+  if (bt->done) (void)hipEventDestroy(bt->done);
+  for (void* p : bt->owned) (void)hipFree(p);
+  bt->owned.clear();
+  if (bt->own_stream && bt->stream) (void)hipStreamDestroy(bt->stream);
+}
+
+template <typename V>
+hipError_t bupload(cum_batch* bt, V** dst, const V* src, size_t count) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, count ? count * sizeof(V) : 16);
+  if (e != hipSuccess) return e;
+  bt->owned.push_back(p);
+  *dst = (V*)p;
+  if (count) e = hipMemcpy(p, src, count * sizeof(V), hipMemcpyHostToDevice);
+  return e;
+}
+
+int batch_launch_all(cum_batch* bt) {
+  for (const auto& g : bt->groups)
+    CUM_TRY(launch_update_batch(bt->prec, g.str, g.vl, bt->d_upd, g.items, g.nitems, g.grid, bt->stream));
+  for (int s = 1; s <= CUM_MAXD; ++s)
+    CUM_TRY(launch_combine_batch(bt->prec, s, bt->d_comb[s], bt->comb_items[s], bt->ncomb[s], bt->comb_grid[s],
+                                 bt->stage_bytes[s], bt->stream));
+  CUM_TRY(launch_norms_batch(bt->d_norm, (int)bt->ctx.size(), bt->stream));
+  return CUM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cum_batch_create(cum_batch** out, cum_ctx* const* ctxs, int m) {
+  if (!out || !ctxs || m < 1 || m > (1 << 20)) return CUM_EINVAL;
+  *out = nullptr;
+  for (int i = 0; i < m; ++i) {
+    if (!ctxs[i]) return CUM_EINVAL;
+    if (!ctxs[i]->ready) return CUM_ESTATE;
+    if (ctxs[i]->prec != ctxs[0]->prec) return CUM_EINVAL;
+    if (ctxs[i]->batch_done) return CUM_EINVAL;  // already in a batch
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return CUM_EINVAL;
+  }
+  cum_batch* bt = new (std::nothrow) cum_batch();
+  if (!bt) return CUM_ENOMEM;
+  bt->ctx.assign(ctxs, ctxs + m);
+  bt->prec = ctxs[0]->prec;
+  auto fail = [&](int rc) {
+    (void)hipGetLastError();
+    batch_release(bt);
+    delete bt;
+    return rc;
+  };
+  for (int i = 0; i < m; ++i)
+    if (hipStreamSynchronize(ctxs[i]->stream) != hipSuccess) return fail(CUM_EDEVICE);
+  if (hipStreamCreateWithFlags(&bt->stream, hipStreamNonBlocking) != hipSuccess) return fail(CUM_EDEVICE);
+  bt->own_stream = true;
+  if (hipEventCreateWithFlags(&bt->done, hipEventDisableTiming) != hipSuccess) return fail(CUM_EDEVICE);
+
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+  }
+  const int pgrid = ncu * 4;
+
+  // per-context update arguments (inputs filled per update)
+  bt->h_upd.resize((size_t)m);
+  for (int i = 0; i < m; ++i) bt->h_upd[(size_t)i] = base_args(ctxs[i]);
+  if (bupload(bt, &bt->d_upd, bt->h_upd.data(), bt->h_upd.size()) != hipSuccess) return fail(CUM_ENOMEM);
+
+  // update items grouped by (LDS stride, vector loader), longest windows first
+  std::vector<int> order((size_t)m);
+  for (int i = 0; i < m; ++i) order[(size_t)i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b2) { return ctxs[a]->t > ctxs[b2]->t; });
+  struct Key { int str; bool vl; };
+  std::vector<Key> keys;
+  for (int i : order) {
+    cum_ctx* c = ctxs[i];
+    const Key k{c->stride, (c->n * (int)c->x_size) % 16 == 0};
+    bool seen = false;
+    for (const auto& q : keys) seen = seen || (q.str == k.str && q.vl == k.vl);
+    if (!seen) keys.push_back(k);
+  }
+  for (const auto& k : keys) {
+    std::vector<UpdItem> items;
+    for (int i : order) {
+      cum_ctx* c = ctxs[i];
+      if (c->stride != k.str || ((c->n * (int)c->x_size) % 16 == 0) != k.vl) continue;
+      if (c->tm != 2 || c->tn != 2) return fail(CUM_EINVAL);
+      std::vector<UpdItem> ci = build_items(c->T, 1, c->d, 32, 32);
+      for (auto& it : ci) {
+        it.ctx = i;
+        items.push_back(it);
+      }
+    }
+    cum_batch::Group g{k.str, k.vl, nullptr, (int)items.size(), 0};
+    g.grid = std::min(g.nitems, pgrid);
+    if (bupload(bt, &g.items, items.data(), items.size()) != hipSuccess) return fail(CUM_ENOMEM);
+    bt->groups.push_back(g);
+  }
+
+  // combine tables per order: one entry per context (unused when d < s)
+  for (int s = 1; s <= CUM_MAXD; ++s) {
+    std::vector<CombArgs> args((size_t)m);
+    std::vector<int64_t> items;
+    size_t stage = 0;
+    for (int i : order) {
+      cum_ctx* c = ctxs[i];
+      if (c->d < s) continue;
+      CombArgs& a = args[(size_t)i];
+      a.b = c->b;
+      a.nbar = c->T.nbar;
+      a.log2b = ((c->b & (c->b - 1)) == 0) ? __builtin_ctz((unsigned)c->b) : -1;
+      a.bs = c->T.ord[s].bk;
+      a.subrank = c->subrank[s];
+      a.s_hi = c->s_hi[s];
+      a.s_lo = c->s_lo[s];
+      a.inv_t = 1.0 / (double)c->t;
+      for (int q = 1; q < s; ++q) a.C[q] = c->C[q];
+      a.Cout = c->C[s];
+      a.mult = c->mult[s];
+      a.partial = c->partial[s];
+      for (int64_t blk = 0; blk < c->T.ord[s].nblocks; ++blk) items.push_back(((int64_t)i << 40) | blk);
+      int64_t tot = 1, bs = 1;
+      for (int q = 0; q < s; ++q) { tot *= (c->b + 1); bs *= c->b; }
+      stage = std::max(stage, (size_t)(tot - 1 - bs) * sizeof(double));
+    }
+    if (items.empty()) continue;
+    bt->ncomb[s] = (int)items.size();
+    bt->comb_grid[s] = std::min(bt->ncomb[s], pgrid * 2);
+    bt->stage_bytes[s] = stage ? stage : 16;
+    if (bupload(bt, &bt->d_comb[s], args.data(), args.size()) != hipSuccess) return fail(CUM_ENOMEM);
+    if (bupload(bt, &bt->comb_items[s], items.data(), items.size()) != hipSuccess) return fail(CUM_ENOMEM);
+  }
+  std::vector<NormArgs> na((size_t)m);
+  for (int i = 0; i < m; ++i) {
+    cum_ctx* c = ctxs[i];
+    na[(size_t)i].d = c->d;
+    na[(size_t)i].kfirst = 1;
+    for (int k = 1; k <= c->d; ++k) {
+      na[(size_t)i].nblocks[k] = c->T.ord[k].nblocks;
+      na[(size_t)i].partial[k] = c->partial[k];
+    }
+    na[(size_t)i].out = c->norms;
+  }
+  if (bupload(bt, &bt->d_norm, na.data(), na.size()) != hipSuccess) return fail(CUM_ENOMEM);
+
+  // capture the whole step once
+  if (hipStreamBeginCapture(bt->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return fail(CUM_EDEVICE);
+  const int lrc = batch_launch_all(bt);
+  hipGraph_t g = nullptr;
+  const hipError_t ce = hipStreamEndCapture(bt->stream, &g);
+  if (lrc != CUM_OK || ce != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(lrc != CUM_OK ? lrc : CUM_EDEVICE);
+  }
+  bt->graph = g;
+  if (hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0) != hipSuccess) return fail(CUM_EDEVICE);
+  for (cum_ctx* c : bt->ctx) c->batch_done = bt->done;
+  *out = bt;
+  return CUM_OK;
+}
+
+int cum_batch_update(cum_batch* bt, const void* const* X_new, const void* const* X_old, const int64_t* p) {
+  if (!bt || !X_new || !X_old || !p) return CUM_EINVAL;
+  const int m = (int)bt->ctx.size();
+  for (int i = 0; i < m; ++i) {
+    cum_ctx* c = bt->ctx[(size_t)i];
+    const int64_t pi = p[i];
+    if (pi < 0 || pi > c->t || pi > kRowChunk) return CUM_EINVAL;
+    if (pi > 0) {
+      if (!X_new[i] || !X_old[i]) return CUM_EINVAL;
+      if (!is_device_ptr(X_new[i]) || !is_device_ptr(X_old[i])) return CUM_EINVAL;
+      const bool vl = (c->n * (int)c->x_size) % 16 == 0;
+      if (vl && (((uintptr_t)X_new[i] | (uintptr_t)X_old[i]) % 16)) return CUM_EINVAL;
+    }
+  }
+  for (cum_ctx* c : bt->ctx)
+    if (c->direct_since_batch) {
+      CUM_TRY(hipStreamSynchronize(c->stream));
+      c->direct_since_batch = false;
+    }
+  for (int i = 0; i < m; ++i) {
+    UpdArgs& a = bt->h_upd[(size_t)i];
+    a.xp = p[i] ? X_new[i] : nullptr;
+    a.xm = p[i] ? X_old[i] : nullptr;
+    a.np = (int)p[i];
+    a.nm = (int)p[i];
+    a.vec = (bt->ctx[(size_t)i]->n * (int)bt->ctx[(size_t)i]->x_size) % 16 == 0;
+  }
+  // pageable source: the copy is staged before the call returns
+  CUM_TRY(hipMemcpyAsync(bt->d_upd, bt->h_upd.data(), bt->h_upd.size() * sizeof(UpdArgs), hipMemcpyHostToDevice,
+                         bt->stream));
+  CUM_TRY(hipGraphLaunch(bt->exec, bt->stream));
+  CUM_TRY(hipEventRecord(bt->done, bt->stream));
+  return CUM_OK;
+}
+
+int cum_batch_sync(cum_batch* bt) {
+  if (!bt) return CUM_EINVAL;
+  CUM_TRY(hipStreamSynchronize(bt->stream));
+  return CUM_OK;
+}
+
+int cum_batch_free(cum_batch* bt) {
+  if (!bt) return CUM_OK;
+  (void)hipStreamSynchronize(bt->stream);
+  batch_release(bt);
+  delete bt;
   return CUM_OK;
 }
 

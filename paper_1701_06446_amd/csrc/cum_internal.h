@@ -44,6 +44,7 @@ struct UpdItem {
   int M, N;         // extents of this pivot GEMM
   int lrow0;        // index of the pivot's first row in the order-k left table
   int rcol0;        // index of the pivot's first column in the order-k right table
+  int ctx;          // batched launches: index of the owning context's descriptor
 };
 
 struct OrderInfo {

@@ -61,4 +61,11 @@ hipError_t launch_update(int prec, int tm, int tn, const UpdArgs& a, int nitems,
 hipError_t launch_combine(int prec, int s, const CombArgs& a, int64_t nblocks, hipStream_t st);
 hipError_t launch_norms(const NormArgs& a, hipStream_t st);
 
+// Batched launches over several contexts (device-resident argument tables).
+hipError_t launch_update_batch(int prec, int str, bool vl, const UpdArgs* ctxs, const UpdItem* items,
+                               int nitems, int grid, hipStream_t st);
+hipError_t launch_combine_batch(int prec, int s, const CombArgs* ctxs, const int64_t* items, int nitems,
+                                int grid, size_t stage_bytes, hipStream_t st);
+hipError_t launch_norms_batch(const NormArgs* ctxs, int m, hipStream_t st);
+
 }  // namespace cum

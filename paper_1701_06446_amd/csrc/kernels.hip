@@ -432,15 +432,13 @@ __device__ __forceinline__ double partition_sum(const double (&cB)[1 << S]) {
 // {1..S} into 2..S parts of prod_B c_B), Alg. 3/4.  The block's weighted
 // sum of squares (Alg. 5) goes to partial[blk].
 template <int S, typename St, bool STAGE>
-__global__ __launch_bounds__(256) void k_combine(CombArgs a) {
+__device__ void combine_block(const CombArgs& a, int64_t blk, double* stage) {
   constexpr int NM = 1 << S;
   constexpr int FULL = NM - 1;
-  extern __shared__ __attribute__((aligned(16))) double stage[];
   __shared__ int64_t subbase[NM];
   __shared__ int lds_off[NM + 1];
   __shared__ double red[256];
   const int tid = threadIdx.x;
-  const int64_t blk = blockIdx.x;
   const int b = a.b;
   const St* shi = (const St*)a.s_hi;
   const St* slo = (const St*)a.s_lo;
@@ -521,12 +519,31 @@ __global__ __launch_bounds__(256) void k_combine(CombArgs a) {
   if (tid == 0) a.partial[blk] = a.mult[blk] * red[0];
 }
 
+template <int S, typename St, bool STAGE>
+__global__ __launch_bounds__(256) void k_combine(CombArgs a) {
+  extern __shared__ __attribute__((aligned(16))) double stage[];
+  combine_block<S, St, STAGE>(a, blockIdx.x, stage);
+}
+
+// Batched form: items[i] = (context << 40) | block, for one order S.
+template <int S, typename St, bool STAGE>
+__global__ __launch_bounds__(256) void k_combine_batch(const CombArgs* __restrict__ ctxs,
+                                                       const int64_t* __restrict__ items, int nitems) {
+  extern __shared__ __attribute__((aligned(16))) double stage[];
+  for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+    const int64_t w = items[i];
+    const CombArgs a = ctxs[w >> 40];
+    combine_block<S, St, STAGE>(a, w & ((int64_t(1) << 40) - 1), stage);
+    __syncthreads();
+  }
+}
+
 // Final norms (Alg. 5 with exponent 2, Eq. (mef)): fro[k] = sqrt(sum of the
 // order's block partials), each order summed by a fixed thread/tree order;
 // nu[k] = fro[k] / fro[2]^(k/2) for k >= 3.  One workgroup of 1024 threads;
 // every thread issues its loads before summing, so an order costs about one
 // memory round trip.
-__global__ __launch_bounds__(1024) void k_norms(NormArgs a) {
+__device__ void norms_block(const NormArgs& a) {
   __shared__ double red[1024];
   __shared__ double fro[CUM_MAXD + 1];
   const int tid = threadIdx.x;
@@ -557,8 +574,80 @@ __global__ __launch_bounds__(1024) void k_norms(NormArgs a) {
   }
 }
 
+__global__ __launch_bounds__(1024) void k_norms(NormArgs a) { norms_block(a); }
+
+// Batched form: workgroup i finishes the norms of context i.
+__global__ __launch_bounds__(1024) void k_norms_batch(const NormArgs* __restrict__ ctxs) {
+  const NormArgs a = ctxs[blockIdx.x];
+  norms_block(a);
+}
+
 // ---------------------------------------------------------------------------
 // Launch wrappers.
+
+// Batched form: many contexts in one persistent launch.  ctxs[] holds each
+// context's arguments (input pointers and row counts refreshed per update),
+// items[] the tiles of all contexts sharing this stride, longest first; every
+// workgroup walks the item list with a grid-sized stride.
+template <int P, int TM, int TN, int STR, bool VL>
+__global__ __launch_bounds__(256) void k_update_batch(const UpdArgs* __restrict__ ctxs,
+                                                      const UpdItem* __restrict__ items, int nitems) {
+  using G = ChunkGeom<P, STR>;
+  static_assert(G::R >= G::UB, "chunk smaller than one unit block per wave");
+  __shared__ __attribute__((aligned(16))) char smem[G::R * STR * G::ES];
+  for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+    const UpdItem it = items[i];
+    const UpdArgs a = ctxs[it.ctx];
+    switch (it.k) {
+      case 1: upd_body<P, 1, 0, TM, TN, STR, VL>(a, it, smem); break;
+      case 2: upd_body<P, 1, 1, TM, TN, STR, VL>(a, it, smem); break;
+      case 3: upd_body<P, 2, 1, TM, TN, STR, VL>(a, it, smem); break;
+      case 4: upd_body<P, 2, 2, TM, TN, STR, VL>(a, it, smem); break;
+      case 5: upd_body<P, 3, 2, TM, TN, STR, VL>(a, it, smem); break;
+      case 6: upd_body<P, 3, 3, TM, TN, STR, VL>(a, it, smem); break;
+      default: break;
+    }
+    __syncthreads();  // the next item reuses the LDS chunk buffer
+  }
+}
+
+template <int P, int STR, bool VL>
+static hipError_t launch_batch_one(const UpdArgs* ctxs, const UpdItem* items, int nitems, int grid,
+                                   hipStream_t st) {
+  if constexpr (ChunkGeom<P, STR>::R >= ChunkGeom<P, STR>::UB) {
+    hipLaunchKernelGGL((k_update_batch<P, 2, 2, STR, VL>), dim3(grid), dim3(256), 0, st, ctxs, items, nitems);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int P>
+static hipError_t launch_batch_p(int str, bool vl, const UpdArgs* ctxs, const UpdItem* items, int nitems,
+                                 int grid, hipStream_t st) {
+  switch (str) {
+    case 36: return vl ? launch_batch_one<P, 36, true>(ctxs, items, nitems, grid, st)
+                       : launch_batch_one<P, 36, false>(ctxs, items, nitems, grid, st);
+    case 68: return vl ? launch_batch_one<P, 68, true>(ctxs, items, nitems, grid, st)
+                       : launch_batch_one<P, 68, false>(ctxs, items, nitems, grid, st);
+    case 132: return vl ? launch_batch_one<P, 132, true>(ctxs, items, nitems, grid, st)
+                        : launch_batch_one<P, 132, false>(ctxs, items, nitems, grid, st);
+    case 260: return vl ? launch_batch_one<P, 260, true>(ctxs, items, nitems, grid, st)
+                        : launch_batch_one<P, 260, false>(ctxs, items, nitems, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_update_batch(int prec, int str, bool vl, const UpdArgs* ctxs, const UpdItem* items,
+                               int nitems, int grid, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  switch (prec) {
+    case PREC_F64: return launch_batch_p<PREC_F64>(str, vl, ctxs, items, nitems, grid, st);
+    case PREC_F32: return launch_batch_p<PREC_F32>(str, vl, ctxs, items, nitems, grid, st);
+    case PREC_BF16X3: return launch_batch_p<PREC_BF16X3>(str, vl, ctxs, items, nitems, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 template <int P, int TM, int TN, int STR>
 static hipError_t launch_one(const UpdArgs& a, int nitems, hipStream_t st) {
@@ -653,6 +742,43 @@ hipError_t launch_combine(int prec, int s, const CombArgs& a, int64_t nblocks, h
   if (nblocks <= 0) return hipSuccess;
   if (prec == PREC_F64) return launch_combine_t<double>(s, a, nblocks, st);
   return launch_combine_t<float>(s, a, nblocks, st);
+}
+
+template <int S, typename St>
+static hipError_t launch_combine_batch_s(const CombArgs* ctxs, const int64_t* items, int nitems, int grid,
+                                         size_t stage_bytes, hipStream_t st) {
+  if (stage_bytes <= COMB_STAGE_BYTES)
+    hipLaunchKernelGGL((k_combine_batch<S, St, true>), dim3(grid), dim3(256), stage_bytes, st, ctxs, items, nitems);
+  else
+    hipLaunchKernelGGL((k_combine_batch<S, St, false>), dim3(grid), dim3(256), 0, st, ctxs, items, nitems);
+  return hipGetLastError();
+}
+
+template <typename St>
+static hipError_t launch_combine_batch_t(int s, const CombArgs* ctxs, const int64_t* items, int nitems, int grid,
+                                         size_t stage_bytes, hipStream_t st) {
+  switch (s) {
+    case 1: return launch_combine_batch_s<1, St>(ctxs, items, nitems, grid, stage_bytes, st);
+    case 2: return launch_combine_batch_s<2, St>(ctxs, items, nitems, grid, stage_bytes, st);
+    case 3: return launch_combine_batch_s<3, St>(ctxs, items, nitems, grid, stage_bytes, st);
+    case 4: return launch_combine_batch_s<4, St>(ctxs, items, nitems, grid, stage_bytes, st);
+    case 5: return launch_combine_batch_s<5, St>(ctxs, items, nitems, grid, stage_bytes, st);
+    case 6: return launch_combine_batch_s<6, St>(ctxs, items, nitems, grid, stage_bytes, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_combine_batch(int prec, int s, const CombArgs* ctxs, const int64_t* items, int nitems,
+                                int grid, size_t stage_bytes, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  if (prec == PREC_F64) return launch_combine_batch_t<double>(s, ctxs, items, nitems, grid, stage_bytes, st);
+  return launch_combine_batch_t<float>(s, ctxs, items, nitems, grid, stage_bytes, st);
+}
+
+hipError_t launch_norms_batch(const NormArgs* ctxs, int m, hipStream_t st) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_norms_batch, dim3(m), dim3(1024), 0, st, ctxs);
+  return hipGetLastError();
 }
 
 hipError_t launch_norms(const NormArgs& a, hipStream_t st) {

@@ -126,6 +126,38 @@ def mixed_exp_stream(n=48, d=6, b=4, t=50000, p=2000, steps=50, workload_id=3) -
     return s
 
 
+def exp_copula_rows(rng, m: int, sigma: np.ndarray) -> np.ndarray:
+    """Gaussian copula with correlation of ``sigma`` and standardized Exp(1)
+    marginals scaled to the variances ``sigma[j, j]``."""
+    from scipy import special
+
+    sd = np.sqrt(np.diag(sigma))
+    z = gaussian_rows(rng, m, sigma) / sd
+    return (-special.log_ndtr(-z) - 1.0) * sd
+
+
+def batched_streams(m=64, steps=40, b=4, workload_id=5, n_max=96):
+    """Independent streams of uneven shape: n uniform in {8, 12, ..., n_max},
+    d uniform in {3, 4}, t uniform in [1000, 20000] rounded to a multiple of
+    20, p = t/20; rows N(0, Sigma_s) or a Gaussian copula with Exp(1)
+    marginals (a coin flip per stream).  One child seed per stream."""
+    root = np.random.SeedSequence([SEED_ROOT, workload_id, 0])
+    out = []
+    for i, child in enumerate(root.spawn(m)):
+        rng = np.random.Generator(np.random.PCG64(child))
+        n = int(rng.choice(np.arange(8, n_max + 1, 4)))
+        d = int(rng.integers(3, 5))
+        t = int(round(rng.uniform(1000, 20000) / 20.0)) * 20
+        p = t // 20
+        sigma = covariance(rng, n)
+        gen = exp_copula_rows if rng.random() < 0.5 else gaussian_rows
+        rows = gen(rng, t + steps * p, sigma)
+        s = Stream("batched_%02d" % i, n, d, min(b, n), t, p, steps, rows)
+        s.kind = gen.__name__
+        out.append(s)
+    return out
+
+
 def stream_by_name(name: str, **kw) -> Stream:
     return {"gaussian": gaussian_stream, "regime_change": regime_change_stream,
             "mixed_exp": mixed_exp_stream}[name](**kw)
