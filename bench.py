@@ -103,6 +103,71 @@ def run_path(prec, s, warmup, steps, prof_steps, check):
     return out
 
 
+def run_batched(steps, warmup, prec="fp32", autotune=True):
+    """64 uneven streams (n in 8..96, d in 3..4, t in 1000..20000, p = t/20)
+    updated together by one captured graph; b per stream from the autotuner."""
+    import torch
+
+    import paper_1701_06446_amd as cum
+    import streams
+    from oracle.element import cumulant_at, sample_elements
+    from paper_1701_06446_amd import autotune as at
+
+    ss = streams.batched_streams(m=64, steps=warmup + steps)
+    t0 = time.perf_counter()
+    if autotune:
+        cache = at.load_cache()
+        for s in ss:
+            s.b = at.choose_b(s.n, s.d, s.t, s.p, prec, cache=cache)
+        at.save_cache(cache)
+    tune_s = time.perf_counter() - t0
+    dt = np.float64 if prec == "fp64" else np.float32
+    rows = [np.ascontiguousarray(s.rows.astype(dt)) for s in ss]
+    dev = [torch.from_numpy(r).to("cuda") for r in rows]
+    ctxs = [cum.cum_init(s.n, s.d, s.b, d[:s.t], prec=prec) for s, d in zip(ss, dev)]
+    bt = cum.cum_batch_create(ctxs)
+    w = 0
+
+    def step():
+        nonlocal w
+        w += 1
+        cum.cum_batch_update(bt, [d[s.t + (w - 1) * s.p:s.t + w * s.p] for s, d in zip(ss, dev)],
+                             [d[(w - 1) * s.p:w * s.p] for s, d in zip(ss, dev)])
+
+    for _ in range(warmup):
+        step()
+    cum.cum_batch_sync(bt)
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    cum.cum_batch_sync(bt)
+    el = time.perf_counter() - t1
+    rows_per_step = sum(s.p for s in ss)
+    flops = sum(2.0 * 2 * s.p * sum(cum.cum_num_elems(s.n, s.b, k) for k in range(1, s.d + 1)) for s in ss)
+    flops_distinct = sum(2.0 * 2 * s.p * at.distinct_elements(s.n, s.d) for s in ss)
+    rng = np.random.default_rng(5)
+    worst = 0.0
+    for i in range(0, 64, 8):
+        s = ss[i]
+        window = rows[i][w * s.p:w * s.p + s.t].astype(np.float64)
+        cache = {}
+        for k in range(2, s.d + 1):
+            offs, idxs = sample_elements(s.n, s.b, k, 6, rng)
+            ref = np.array([cumulant_at(window, idx, cache) for idx in idxs])
+            g = cum.cum_get(ctxs[i], k)[offs]
+            worst = max(worst, float(np.linalg.norm(g - ref) / np.linalg.norm(ref)))
+    cum.cum_batch_free(bt)
+    for c in ctxs:
+        cum.cum_free(c)
+    return {"streams": 64, "steps": steps, "warmup": warmup, "prec": prec,
+            "rows_per_s": rows_per_step * steps / el, "updates_per_s": 64 * steps / el,
+            "ms_per_step": el / steps * 1e3, "rows_per_step": rows_per_step,
+            "tflops_algorithmic": flops * steps / el / 1e12,
+            "tflops_distinct_elements": flops_distinct * steps / el / 1e12,
+            "b_choice": {str(b): sum(1 for s in ss if s.b == b) for b in (1, 2, 4, 8)},
+            "autotune_s": tune_s, "err_sampled_max": worst, "tol": TOL[prec]}
+
+
 def cpu_baseline(s, budget_s=12.0):
     """The oracle (as it stands) on the host cores: sliding steps of p=1000 rows
     at n=60, d=4, b=4 from a 2000-row start window, each step = compensated
@@ -134,6 +199,7 @@ def main():
     ap.add_argument("--prof-steps", type=int, default=20)
     ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-stream batched leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -181,6 +247,10 @@ def main():
         "paths": res,
         "device": torch.cuda.get_device_name(0),
     }
+    if not args.no_batched:
+        print("[bench] batched: 64 streams, 40 steps", file=sys.stderr, flush=True)
+        line["batched"] = run_batched(steps=40, warmup=3)
+        print("[bench] batched: %.3f ms/step" % line["batched"]["ms_per_step"], file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(s)
