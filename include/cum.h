@@ -187,6 +187,23 @@ int cum_batch_sync(cum_batch *batch);
 int cum_batch_free(cum_batch *batch);
 
 /*
+ * cum_loss_grad -- the contrast L = sum_{k=1..d} w[k] ||C_k(Y)||_F^2 of the
+ * single window Y = X W^T (X: t x n, W: n x n, row-major FP32 device
+ * memory) and its gradients dL/dX (t x n) and dL/dW (n x n), FP32 device
+ * memory owned by the caller.  w holds d+1 host doubles (w[0] unused).
+ * Forward: FP32 moment contraction, FP64 combine (Alg. 3/4) and norms
+ * (Alg. 5); reverse: FP64 (Alg. 4 backwards, then the derivative of
+ * Eq. (mom)), with FP64 atomic additions in the reverse combine (results
+ * reproducible up to their order).  L (host) receives the loss.
+ * Synchronises `hip_stream`; allocates and frees its own temporaries.
+ * CUM_ESIZE when n > 64, when orders 1..d hold more than 2^24 stored
+ * elements, or when the reverse combine's LDS would exceed 64 KB
+ * ((b+1)^s - 1 - b^s > 4096 for some s <= d).
+ */
+int cum_loss_grad(int n, int d, int b, const float *X, int64_t t, const float *W, const double *w,
+                  double *L, float *dX, float *dW, void *hip_stream);
+
+/*
  * cum_plan_coverage -- host-only check of the update's pivot decomposition
  * (no GPU needed): for order k, counts how many (pivot, row, column)
  * products of the update land on each stored element (written to `hits`,

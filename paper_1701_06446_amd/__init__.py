@@ -33,7 +33,7 @@ EXPORTS = ("cum_init", "cum_update", "cum_get", "cum_get_moments", "cum_norms",
            "cum_norms_device", "cum_sync", "cum_free", "cum_num_blocks", "cum_num_elems",
            "cum_strerror", "cum_last_error", "cum_plan_coverage", "cum_plan_items",
            "cum_profile_enable", "cum_profile_read", "cum_batch_create", "cum_batch_update",
-           "cum_batch_sync", "cum_batch_free")
+           "cum_batch_sync", "cum_batch_free", "cum_loss_grad")
 
 
 class CumError(RuntimeError):
@@ -71,6 +71,8 @@ def _load():
         "cum_batch_update": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64)]),
         "cum_batch_sync": (i32, [vp]),
         "cum_batch_free": (i32, [vp]),
+        "cum_loss_grad": (i32, [i32, i32, i32, vp, i64, vp, ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_double), vp, vp, vp]),
         "cum_profile_read": (i32, [vp, ctypes.POINTER(i64), pd]),
     }
     for name, (res, args) in sig.items():
@@ -268,3 +270,48 @@ def cum_batch_free(batch: Batch):
     if batch.handle:
         _check(_lib.cum_batch_free(batch.handle), "cum_batch_free")
         batch.handle = None
+
+
+def cum_loss_grad(X, W, d=4, b=4, weights=None, stream=None):
+    """L = sum_k weights[k] ||C_k(X W^T)||_F^2 and (dL/dX, dL/dW) from the HIP
+    adjoint.  X: (t, n), W: (n, n), contiguous float32 device tensors."""
+    import torch
+
+    weights = weights or {3: 1.0, 4: 1.0}
+    t, n = X.shape
+    if X.dtype != torch.float32 or W.dtype != torch.float32 or W.shape != (n, n) or not X.is_cuda:
+        raise ValueError("X (t, n) and W (n, n) must be float32 device tensors")
+    X, W = X.contiguous(), W.contiguous()
+    dX, dW = torch.empty_like(X), torch.empty_like(W)
+    w = (ctypes.c_double * (d + 1))(*[float(weights.get(k, 0.0)) for k in range(d + 1)])
+    L = ctypes.c_double()
+    st = torch.cuda.current_stream().cuda_stream if stream is None else stream
+    _check(_lib.cum_loss_grad(n, d, b, X.data_ptr(), t, W.data_ptr(), w, ctypes.byref(L), dX.data_ptr(),
+                              dW.data_ptr(), ctypes.c_void_p(st)), "cum_loss_grad")
+    return L.value, dX, dW
+
+
+def _cum_loss_function():
+    import torch
+
+    class CumLoss(torch.autograd.Function):
+        """L = sum_k w_k ||C_k(X W^T)||_F^2 with the gradients of the HIP adjoint
+        (computed together with the loss, scaled by the incoming gradient)."""
+
+        @staticmethod
+        def forward(ctx, X, W, d=4, b=4, weights=((3, 1.0), (4, 1.0))):
+            L, dX, dW = cum_loss_grad(X.detach(), W.detach(), d, b, dict(weights))
+            ctx.save_for_backward(dX, dW)
+            return torch.tensor(L, dtype=torch.float64, device=X.device)
+
+        @staticmethod
+        def backward(ctx, gL):
+            dX, dW = ctx.saved_tensors
+            g = gL.to(torch.float32)
+            return g * dX, g * dW, None, None, None
+
+    return CumLoss
+
+
+if _torch is not None:
+    CumLoss = _cum_loss_function()

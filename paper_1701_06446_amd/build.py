@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcum.so")
-SOURCES = ["api.cpp", "tables.cpp", "kernels.hip"]
+SOURCES = ["api.cpp", "tables.cpp", "kernels.hip", "adjoint.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep the compiler from emitting packed FP32 vector instructions

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "../../include/cum.h"
+#include "adjoint.h"
 #include "kernels.h"
 #include "tables.h"
 
@@ -766,6 +767,166 @@ int cum_batch_free(cum_batch* bt) {
   batch_release(bt);
   delete bt;
   return CUM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Adjoint: L = sum_k w_k ||C_k(X W^T)||_F^2 and its gradients.
+
+namespace {
+
+// Per data column j, every stored element (order s, offset) containing j,
+// the number of its indices equal to j and its other s-1 indices.
+void build_ybar_entries(const Tables& T, std::vector<int64_t>& colptr, std::vector<YbarEntry>& entries) {
+  const int n = T.n, b = T.b;
+  std::vector<std::vector<YbarEntry>> per(n);
+  for (int s = 1; s <= T.d; ++s) {
+    const OrderInfo& o = T.ord[s];
+    for (int64_t r = 0; r < o.nblocks; ++r) {
+      for (int64_t e = 0; e < o.bk; ++e) {
+        int idx[CUM_MAXD];
+        int64_t rem = e;
+        bool pad = false;
+        for (int q = s - 1; q >= 0; --q) {
+          idx[q] = T.tuples[s][(size_t)r * s + q] * b + (int)(rem % b);
+          rem /= b;
+          pad = pad || idx[q] >= n;
+        }
+        if (pad) continue;
+        for (int q = 0; q < s; ++q) {
+          bool first = true;
+          for (int u = 0; u < q; ++u) first = first && idx[u] != idx[q];
+          if (!first) continue;
+          YbarEntry en{};
+          en.off = (int32_t)(r * o.bk + e);
+          en.s = (uint8_t)s;
+          int cnt = 0, k = 0;
+          bool skipped = false;
+          for (int u = 0; u < s; ++u) {
+            if (idx[u] == idx[q]) ++cnt;
+            if (idx[u] == idx[q] && !skipped) { skipped = true; continue; }
+            en.oth[k++] = (uint8_t)idx[u];
+          }
+          en.cnt = (uint8_t)cnt;
+          per[(size_t)idx[q]].push_back(en);
+        }
+      }
+    }
+  }
+  colptr.assign((size_t)n + 1, 0);
+  entries.clear();
+  for (int j = 0; j < n; ++j) {
+    colptr[(size_t)j] = (int64_t)entries.size();
+    entries.insert(entries.end(), per[(size_t)j].begin(), per[(size_t)j].end());
+  }
+  colptr[(size_t)n] = (int64_t)entries.size();
+}
+
+}  // namespace
+
+extern "C" {
+
+int cum_loss_grad(int n, int d, int b, const float* X, int64_t t, const float* W, const double* w, double* L,
+                  float* dX, float* dW, void* hip_stream) {
+  int rc = check_shape(n, d, b);
+  if (rc != CUM_OK) return rc;
+  if (!X || !W || !w || !L || !dX || !dW || t < 1 || t > ((int64_t)1 << 31)) return CUM_EINVAL;
+  // Y_bar stages 256 rows of Y (256 n floats) in LDS; the host table of
+  // (element, column) pairs holds up to d entries per stored element
+  if (n > 64) return CUM_ESIZE;
+  {
+    Tables probe;
+    if (build_tables(n, b, d, probe) != 0) return CUM_EINVAL;
+    int64_t tot = 0;
+    for (int k = 1; k <= d; ++k) tot += probe.ord[k].nelems;
+    if (tot > ((int64_t)1 << 24)) return CUM_ESIZE;
+  }
+  // the reverse combine keeps staged cumulants and their gradients in LDS
+  for (int s = 2; s <= d; ++s) {
+    int64_t tot = 1, bs = 1;
+    for (int q = 0; q < s; ++q) { tot *= (b + 1); bs *= b; }
+    if ((tot - 1 - bs) * 2 * (int64_t)sizeof(double) > 65536) return CUM_ESIZE;
+  }
+  if (!is_device_ptr(X) || !is_device_ptr(W) || !is_device_ptr(dX) || !is_device_ptr(dW)) return CUM_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  std::vector<void*> tmp;
+  cum_ctx* c = nullptr;
+  auto done = [&](int r) {
+    (void)hipStreamSynchronize(st);
+    for (void* p : tmp) (void)hipFree(p);
+    if (c) cum_free(c);
+    return r;
+  };
+  auto alloc = [&](void** p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes ? bytes : 16);
+    if (e == hipSuccess) tmp.push_back(*p);
+    return e;
+  };
+  float* Y = nullptr;
+  hipError_t e = alloc((void**)&Y, (size_t)t * n * sizeof(float));
+  if (e != hipSuccess) return done(map_err(e));
+  if ((e = launch_linear(X, W, Y, t, n, st)) != hipSuccess) return done(map_err(e));
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return done(map_err(e));
+  rc = cum_init(&c, n, d, b, Y, t, CUM_FP32, hip_stream);
+  if (rc != CUM_OK) return done(rc);
+  std::vector<double> fro((size_t)d + 1), nu((size_t)d + 1);
+  rc = cum_norms(c, fro.data(), nu.data());
+  if (rc != CUM_OK) return done(rc);
+  double loss = 0.0;
+  for (int k = 1; k <= d; ++k)
+    if (w[k] != 0.0) loss += w[k] * fro[(size_t)k] * fro[(size_t)k];
+  *L = loss;
+
+  double* Cbar[CUM_MAXD + 1] = {};
+  for (int k = 1; k <= d; ++k) {
+    const OrderInfo& o = c->T.ord[k];
+    if ((e = alloc((void**)&Cbar[k], (size_t)o.nelems * sizeof(double))) != hipSuccess) return done(map_err(e));
+    if ((e = launch_cbar_init(c->C[k], c->mult[k], Cbar[k], o.nelems, o.bk, 2.0 * w[k], st)) != hipSuccess)
+      return done(map_err(e));
+  }
+  for (int s = d; s >= 2; --s) {
+    RevArgs ra{};
+    ra.b = b;
+    ra.bs = c->T.ord[s].bk;
+    ra.subrank = c->subrank[s];
+    for (int k = 1; k <= d; ++k) {
+      ra.C[k] = c->C[k];
+      ra.Cbar[k] = Cbar[k];
+    }
+    int64_t tot = 1, bs = 1;
+    for (int q = 0; q < s; ++q) { tot *= (b + 1); bs *= b; }
+    const size_t lds = (size_t)(tot - 1 - bs) * 2 * sizeof(double);
+    if ((e = launch_combine_rev(s, ra, c->T.ord[s].nblocks, lds, st)) != hipSuccess) return done(map_err(e));
+  }
+  std::vector<int64_t> colptr;
+  std::vector<YbarEntry> entries;
+  build_ybar_entries(c->T, colptr, entries);
+  int64_t* d_colptr = nullptr;
+  YbarEntry* d_entries = nullptr;
+  if ((e = alloc((void**)&d_colptr, colptr.size() * sizeof(int64_t))) != hipSuccess) return done(map_err(e));
+  if ((e = alloc((void**)&d_entries, entries.size() * sizeof(YbarEntry))) != hipSuccess) return done(map_err(e));
+  if ((e = hipMemcpy(d_colptr, colptr.data(), colptr.size() * sizeof(int64_t), hipMemcpyHostToDevice)) != hipSuccess)
+    return done(map_err(e));
+  if (!entries.empty() &&
+      (e = hipMemcpy(d_entries, entries.data(), entries.size() * sizeof(YbarEntry), hipMemcpyHostToDevice)) !=
+          hipSuccess)
+    return done(map_err(e));
+  double* Ybar = nullptr;
+  if ((e = alloc((void**)&Ybar, (size_t)t * n * sizeof(double))) != hipSuccess) return done(map_err(e));
+  YbarArgs ya{};
+  ya.n = n;
+  ya.t = t;
+  ya.inv_t = 1.0 / (double)t;
+  ya.Y = Y;
+  for (int k = 1; k <= d; ++k) ya.Mbar[k] = Cbar[k];
+  ya.colptr = d_colptr;
+  ya.entries = d_entries;
+  ya.Ybar = Ybar;
+  if ((e = launch_ybar(ya, st)) != hipSuccess) return done(map_err(e));
+  if ((e = launch_dx_dw(Ybar, X, W, dX, dW, t, n, st)) != hipSuccess) return done(map_err(e));
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return done(map_err(e));
+  return done(CUM_OK);
 }
 
 }  // extern "C"

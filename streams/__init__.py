@@ -158,6 +158,18 @@ def batched_streams(m=64, steps=40, b=4, workload_id=5, n_max=96):
     return out
 
 
+def adjoint_workload(t=10000, n=32, workload_id=4):
+    """(X, W) for the ICA-style contrast: X = T A^T with T i.i.d. standardized
+    Student-t(5) sources and A = G_A / sqrt(n); W = Q + 0.05 G_W / sqrt(n)
+    with Q Haar-orthogonal (near-orthogonal unmixing)."""
+    rng = rng_for(workload_id)
+    T = rng.standard_t(5, size=(t, n)) / np.sqrt(5.0 / 3.0)
+    A = rng.standard_normal((n, n)) / np.sqrt(n)
+    Q = haar_orthogonal(rng, n)
+    W = Q + 0.05 * rng.standard_normal((n, n)) / np.sqrt(n)
+    return T @ A.T, W
+
+
 def stream_by_name(name: str, **kw) -> Stream:
     return {"gaussian": gaussian_stream, "regime_change": regime_change_stream,
             "mixed_exp": mixed_exp_stream}[name](**kw)
