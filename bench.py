@@ -32,6 +32,47 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 1e-4}
 
 
+# HBM bytes per k_update launch at this workload from two rocprofv3 --pmc
+# passes (FETCH_SIZE, WRITE_SIZE; mean over the sliding-update dispatches),
+# each scaled by the ratio of known bytes to the same counter on a plain
+# device copy.  Valid only for the kernel source they were taken on.
+TRAFFIC = {"prec": "fp32",
+           "kernels_sha256": "e012c3c2901fe30759e892b5b30eaac7c96182a8208bb66032135eb7f24e391a",
+           "fetch_bytes": 5568.94 * 1024 * 1.99988,   # FETCH_SIZE KiB x (256 MiB / 131078.5 KiB)
+           "write_bytes": 6475.94 * 1024 * 1.00000}   # WRITE_SIZE KiB x (256 MiB / 262144.0 KiB)
+
+
+def kernels_sha256() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_1701_06446_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_for(prec: str):
+    if TRAFFIC["kernels_sha256"] != kernels_sha256() or TRAFFIC["prec"] != prec:
+        return None
+    return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+
+
+def copy_calibration(mib: int):
+    """A plain elementwise pass (dst = -src) over mib MiB, three times: a
+    reference for the FETCH_SIZE / WRITE_SIZE counters, each pass reading and
+    writing mib MiB (an elementwise kernel, where a same-type copy could go to
+    a DMA engine that the counters do not see)."""
+    import torch
+
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    return {"bytes_each_way": mib << 20, "copies": 3}
+
+
 def algorithmic_flops_per_update(p: int) -> float:
     """One FMA per stored pyramid element per signed row: 2 * (2p) * sum_k E_k."""
     import paper_1701_06446_amd as cum
@@ -56,7 +97,7 @@ def sampled_error(ctx, window: np.ndarray, rng, count: int = 40):
     return worst
 
 
-def run_path(prec, s, warmup, steps, prof_steps, check):
+def run_path(prec, s, warmup, steps, check):
     import torch
 
     import paper_1701_06446_amd as cum
@@ -76,22 +117,36 @@ def run_path(prec, s, warmup, steps, prof_steps, check):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
+    # timed region: HIP events bracket the update kernel on the context's stream
+    cum.cum_profile_enable(ctx, ["update"])
     t0 = time.perf_counter()
     for _ in range(steps):
         step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    cum.cum_profile_enable(ctx, True)
-    for _ in range(prof_steps):
-        step()
     prof = cum.cum_profile_read(ctx)
     cum.cum_profile_enable(ctx, False)
+    # the same number of steps without events (their overhead), then a few
+    # with every kernel class bracketed (the smaller kernels' durations)
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    plain = time.perf_counter() - t1
+    cum.cum_profile_enable(ctx, True)
+    for _ in range(10):
+        step()
+    allk = cum.cum_profile_read(ctx)
+    cum.cum_profile_enable(ctx, False)
+    prof = {"update": prof["update"], "combine": allk["combine"], "norms": allk["norms"]}
     out = {
         "ms_per_step": elapsed / steps * 1e3,
         "updates_per_s": steps / elapsed,
         "rows_per_s": steps * P / elapsed,
+        "ms_per_step_without_kernel_events": plain / steps * 1e3,
         "kernel_ms": {k: (v[1] / v[0] if v[0] else None) for k, v in prof.items()},
-        "launches_per_step": {k: v[0] / prof_steps for k, v in prof.items()},
+        "launches_per_step": {"update": prof["update"][0] / steps, "combine": prof["combine"][0] / 10,
+                              "norms": prof["norms"][0] / 10},
     }
     if check:
         window = rows[w * P: w * P + T].astype(np.float64)
@@ -196,7 +251,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--paths", default="fp64,fp32,bf16x3", help="precisions to measure")
-    ap.add_argument("--prof-steps", type=int, default=20)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of MIB MiB three times (for scaling HBM counters)")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-stream batched leg")
@@ -210,14 +266,14 @@ def main():
 
     import streams
 
-    total_steps = max(200, args.warmup + args.steps + args.prof_steps)
+    total_steps = max(200, args.warmup + 2 * args.steps + 10)
     s = streams.regime_change_stream(n=N, d=D, b=B, t=T, p=P, steps=total_steps, switch=100)
     paths = [p for p in args.paths.split(",") if p and p != args.prec] + [args.prec]
     res = {}
     for prec in paths:
         print("[bench] path %s: warmup %d, %d timed steps" % (prec, args.warmup, args.steps),
               file=sys.stderr, flush=True)
-        res[prec] = run_path(prec, s, args.warmup, args.steps, args.prof_steps, not args.no_check)
+        res[prec] = run_path(prec, s, args.warmup, args.steps, not args.no_check)
         print("[bench] path %s: %.3f ms/step" % (prec, res[prec]["ms_per_step"]), file=sys.stderr, flush=True)
     main = res[args.prec]
     flops = algorithmic_flops_per_update(P)
@@ -243,10 +299,12 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "k_update", "achieved": achieved,
                      "peak": PEAK_TFLOPS[args.prec], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS[args.prec],
-                     "flops_per_launch": flops, "kernel_ms": upd_ms, "traffic": None},
+                     "flops_per_launch": flops, "kernel_ms": upd_ms, "traffic": traffic_for(args.prec)},
         "paths": res,
         "device": torch.cuda.get_device_name(0),
     }
+    if args.copy_calibration:
+        line["copy_calibration"] = copy_calibration(args.copy_calibration)
     if not args.no_batched:
         print("[bench] batched: 64 streams, 40 steps", file=sys.stderr, flush=True)
         line["batched"] = run_batched(steps=40, warmup=3)

@@ -132,9 +132,11 @@ int cum_norms(cum_ctx *ctx, double *fro, double *nu);
 int cum_norms_device(cum_ctx *ctx, const double **dev_ptr);
 
 /*
- * cum_profile_enable -- when on != 0, every kernel launch of this context is
- * bracketed by HIP events on the context's stream (adds a small gap between
- * launches).  Synchronises and clears earlier records.
+ * cum_profile_enable -- `on` is a mask of kernel classes (bit 0 = moment
+ * update, bit 1 = cumulant combine, bit 2 = norms; 0 switches profiling
+ * off): every launch of a selected class is bracketed by HIP events on the
+ * context's stream (each pair adds a short gap between launches).
+ * Synchronises and clears earlier records.
  */
 int cum_profile_enable(cum_ctx *ctx, int on);
 

@@ -212,8 +212,21 @@ def cum_plan_items(n: int, d: int, b: int) -> int:
     return int(_lib.cum_plan_items(n, d, b))
 
 
-def cum_profile_enable(ctx: Context, on: bool = True):
-    _check(_lib.cum_profile_enable(ctx.handle, 1 if on else 0), "cum_profile_enable")
+PROFILE_CLASSES = {"update": 1, "combine": 2, "norms": 4}
+
+
+def cum_profile_enable(ctx: Context, on=True):
+    """on: True (every kernel class), False, or an iterable of class names
+    ("update", "combine", "norms") to bracket with HIP events."""
+    if on is True:
+        mask = 7
+    elif not on:
+        mask = 0
+    else:
+        mask = 0
+        for name in on:
+            mask |= PROFILE_CLASSES[name]
+    _check(_lib.cum_profile_enable(ctx.handle, mask), "cum_profile_enable")
 
 
 def cum_profile_read(ctx: Context):

@@ -56,10 +56,12 @@ struct cum_ctx {
   // whether the context was updated directly since (the batch then waits)
   hipEvent_t batch_done = nullptr;
   bool direct_since_batch = false;
-  // optional per-kernel timing: (class, start, stop) per launch
-  bool profiling = false;
+  // optional per-kernel timing: (class, start, stop) per launch of the
+  // classes in profile_mask; events are recycled through a pool
+  int profile_mask = 0;
   struct Ev { int cls; hipEvent_t a, b; };
   std::vector<Ev> events;
+  std::vector<hipEvent_t> event_pool;
 };
 
 namespace {
@@ -129,14 +131,16 @@ bool is_device_ptr(const void* p) {
 
 void drop_events(cum_ctx* c) {
   for (auto& e : c->events) {
-    (void)hipEventDestroy(e.a);
-    (void)hipEventDestroy(e.b);
+    c->event_pool.push_back(e.a);
+    c->event_pool.push_back(e.b);
   }
   c->events.clear();
 }
 
 void release(cum_ctx* c) {
   drop_events(c);
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  c->event_pool.clear();
   for (void* p : c->owned) (void)hipFree(p);
   c->owned.clear();
   if (c->stage) (void)hipFree(c->stage);
@@ -148,15 +152,32 @@ int check_shape(int n, int d, int b) {
   return CUM_OK;
 }
 
-// Brackets one launch with HIP events when profiling is on (class 0 =
-// update, 1 = combine, 2 = norms).
+hipEvent_t pooled_event(cum_ctx* c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+// Brackets one launch with HIP events when its class (0 = update,
+// 1 = combine, 2 = norms) is being profiled.
 struct Timed {
   cum_ctx* c;
   int cls;
   hipEvent_t a = nullptr, b = nullptr;
   Timed(cum_ctx* ctx, int k) : c(ctx), cls(k) {
-    if (!c->profiling) return;
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
+    if (!(c->profile_mask & (1 << cls))) return;
+    a = pooled_event(c);
+    b = pooled_event(c);
+    if (!a || !b) {
+      if (a) c->event_pool.push_back(a);
+      if (b) c->event_pool.push_back(b);
+      a = b = nullptr;
+      return;
+    }
     (void)hipEventRecord(a, c->stream);
   }
   ~Timed() {
@@ -493,7 +514,7 @@ int cum_profile_enable(cum_ctx* c, int on) {
   if (!c->ready) return CUM_ESTATE;
   CUM_TRY(hipStreamSynchronize(c->stream));
   drop_events(c);
-  c->profiling = on != 0;
+  c->profile_mask = on & 7;
   return CUM_OK;
 }
 
