@@ -58,6 +58,7 @@ struct cum_ctx {
   bool direct_since_batch = false;
   // optional per-kernel timing: (class, start, stop) per launch of the
   // classes in profile_mask; events are recycled through a pool
+  void* zero = nullptr;  // UPD_ZERO_BYTES zeros: padding source of the update's direct loads
   int profile_mask = 0;
   struct Ev { int cls; hipEvent_t a, b; };
   std::vector<Ev> events;
@@ -203,6 +204,7 @@ UpdArgs base_args(cum_ctx* c) {
   UpdArgs a{};
   a.n = c->n;
   a.items = c->items;
+  a.zero = c->zero;
   for (int k = 1; k <= c->d; ++k) {
     a.left[k] = c->left[k];
     a.right[k] = c->right[k];
@@ -225,7 +227,7 @@ int run_contraction(cum_ctx* c, const char* xp, int64_t np, const char* xm, int6
     a.nm = (int)cm;
     a.vec = ((c->n * c->x_size) % 16 == 0) && ((uintptr_t)a.xp % 16 == 0) && ((uintptr_t)a.xm % 16 == 0);
     Timed tm(c, 0);
-    CUM_TRY(launch_update(c->prec, c->tm, c->tn, a, c->nitems, c->stream));
+    CUM_TRY(launch_update(c->prec, c->tm, c->tn, c->d, a, c->nitems, c->stream));
   }
   return CUM_OK;
 }
@@ -378,6 +380,8 @@ int cum_init(cum_ctx** out, int n, int d, int b, const void* X, int64_t t, int p
   }
   if ((e = upload(c, &c->items, items, &used)) != hipSuccess) return fail(e);
   if ((e = dalloc(c, (void**)&c->norms, (size_t)2 * (d + 1) * 8, &used)) != hipSuccess) return fail(e);
+  if ((e = dalloc(c, &c->zero, UPD_ZERO_BYTES, &used)) != hipSuccess) return fail(e);
+  if ((e = hipMemsetAsync(c->zero, 0, UPD_ZERO_BYTES, c->stream)) != hipSuccess) return fail(e);
 
   // the window, on the device
   const char* xw = (const char*)X;
@@ -557,7 +561,7 @@ struct cum_batch {
   bool own_stream = false;
   std::vector<UpdArgs> h_upd;
   UpdArgs* d_upd = nullptr;
-  struct Group { int str; bool vl; UpdItem* items; int nitems; int grid; };
+  struct Group { int str; bool vl; int kmax; UpdItem* items; int nitems; int grid; };
   std::vector<Group> groups;
   CombArgs* d_comb[CUM_MAXD + 1] = {};
   int64_t* comb_items[CUM_MAXD + 1] = {};
@@ -597,7 +601,7 @@ hipError_t bupload(cum_batch* bt, V** dst, const V* src, size_t count) {
 
 int batch_launch_all(cum_batch* bt) {
   for (const auto& g : bt->groups)
-    CUM_TRY(launch_update_batch(bt->prec, g.str, g.vl, bt->d_upd, g.items, g.nitems, g.grid, bt->stream));
+    CUM_TRY(launch_update_batch(bt->prec, g.str, g.vl, g.kmax, bt->d_upd, g.items, g.nitems, g.grid, bt->stream));
   for (int s = 1; s <= CUM_MAXD; ++s)
     CUM_TRY(launch_combine_batch(bt->prec, s, bt->d_comb[s], bt->comb_items[s], bt->ncomb[s], bt->comb_grid[s],
                                  bt->stage_bytes[s], bt->stream));
@@ -663,17 +667,19 @@ int cum_batch_create(cum_batch** out, cum_ctx* const* ctxs, int m) {
   }
   for (const auto& k : keys) {
     std::vector<UpdItem> items;
+    int kmax = 1;
     for (int i : order) {
       cum_ctx* c = ctxs[i];
       if (c->stride != k.str || ((c->n * (int)c->x_size) % 16 == 0) != k.vl) continue;
       if (c->tm != 2 || c->tn != 2) return fail(CUM_EINVAL);
+      kmax = std::max(kmax, c->d);
       std::vector<UpdItem> ci = build_items(c->T, 1, c->d, 32, 32);
       for (auto& it : ci) {
         it.ctx = i;
         items.push_back(it);
       }
     }
-    cum_batch::Group g{k.str, k.vl, nullptr, (int)items.size(), 0};
+    cum_batch::Group g{k.str, k.vl, kmax, nullptr, (int)items.size(), 0};
     g.grid = std::min(g.nitems, pgrid);
     if (bupload(bt, &g.items, items.data(), items.size()) != hipSuccess) return fail(CUM_ENOMEM);
     bt->groups.push_back(g);

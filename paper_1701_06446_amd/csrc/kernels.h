@@ -13,6 +13,8 @@ enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };
 // the four waves of a workgroup split the rows of every LDS chunk between
 // them and are reduced in a fixed order at the end.
 constexpr int UPD_X_BYTES = 32768;     // bytes of data rows per LDS chunk
+constexpr int UPD_DIRECT_BYTES = 17408; // bytes per buffer of the double-buffered direct path
+constexpr int UPD_ZERO_BYTES = 256;     // zeroed device block the direct path reads for padding
 
 struct UpdArgs {
   const void* xp;           // rows entering the window (+1), row-major np x n
@@ -21,6 +23,7 @@ struct UpdArgs {
   int n;                    // data columns (LDS rows hold exactly n values)
   int vec;                  // 1: rows and both bases allow 16-byte copies
   const UpdItem* items;
+  const void* zero;         // UPD_ZERO_BYTES of zeros (direct-path padding source)
   const LeftCol* left[CUM_MAXD + 1];
   const RightCol* right[CUM_MAXD + 1];
   void* s_hi[CUM_MAXD + 1]; // running window sums, compensated pair
@@ -57,12 +60,12 @@ bool update_tile_supported(int tm, int tn);
 int update_lds_stride(int n);
 // Rows per LDS chunk for a precision and stride (0: not supported).
 int update_chunk_rows(int prec, int str);
-hipError_t launch_update(int prec, int tm, int tn, const UpdArgs& a, int nitems, hipStream_t st);
+hipError_t launch_update(int prec, int tm, int tn, int kmax, const UpdArgs& a, int nitems, hipStream_t st);
 hipError_t launch_combine(int prec, int s, const CombArgs& a, int64_t nblocks, hipStream_t st);
 hipError_t launch_norms(const NormArgs& a, hipStream_t st);
 
 // Batched launches over several contexts (device-resident argument tables).
-hipError_t launch_update_batch(int prec, int str, bool vl, const UpdArgs* ctxs, const UpdItem* items,
+hipError_t launch_update_batch(int prec, int str, bool vl, int kmax, const UpdArgs* ctxs, const UpdItem* items,
                                int nitems, int grid, hipStream_t st);
 hipError_t launch_combine_batch(int prec, int s, const CombArgs* ctxs, const int64_t* items, int nitems,
                                 int grid, size_t stage_bytes, hipStream_t st);

@@ -79,6 +79,27 @@ template <int P, int STR> struct ChunkGeom {
   static constexpr int R = (UPD_X_BYTES / ((STR - 4) * ES)) / UB * UB;  // 0: shape not supported
 };
 
+// Direct path (f32/f64 with 16-byte rows): every wave copies its own rows
+// of each chunk (RW = R/4 rows, the only rows its k-steps read) from global
+// memory straight into two private LDS buffers, the next chunk arriving while
+// the current one is multiplied; the waves never wait for each other.  R rows
+// per chunk (a multiple of 32 when it can be, else 16), row stride STR as in
+// ChunkGeom; SU 16-byte units per LDS row; a wave's buffer is rounded up to
+// whole 64-lane loads (WU units).  Buffer b of wave w starts at unit
+// (4 b + w) WU.
+template <int P, int STR> struct DirectGeom {
+  static constexpr int ES = (P == PREC_F64) ? 8 : 4;
+  static constexpr int X = UPD_DIRECT_BYTES / (STR * ES);
+  static constexpr int R = X >= 32 ? X / 32 * 32 : 16;
+  static constexpr int RW = R / 4;
+  static constexpr int SU = STR * ES / 16;
+  static constexpr int WU = (RW * SU + 63) / 64 * 64;
+  static constexpr int BUFB = 4 * WU * 16;
+  static constexpr int SMEM = 2 * BUFB;
+};
+
+template <int V> struct IntC { static constexpr int value = V; };
+
 constexpr int PREF_UNITS = UPD_X_BYTES / 16 / 256;
 
 struct RegChunk {
@@ -102,8 +123,10 @@ __device__ __forceinline__ void chunk_slots(int (&slot)[PREF_UNITS], int n) {
   }
 }
 
-// 16-byte units of chunk `ci` into registers (vector path: n*esize % 16 == 0);
-// chunks past the last (ci >= nch) and units past the chunk's rows read zeros.
+// 16-byte units of chunk `ci` into registers (vector path: n*esize % 16 == 0).
+// A full chunk loads without predicates (units past the chunk's last row
+// re-read its last unit and are never stored); the last chunk of each sign
+// and chunks past the last (ci >= nch) read zeros past their rows.
 template <int P, int STR>
 __device__ __forceinline__ void fetch_chunk(RegChunk& rc, const UpdArgs& a, int ci, int ncp, int nch) {
   using G = ChunkGeom<P, STR>;
@@ -111,11 +134,17 @@ __device__ __forceinline__ void fetch_chunk(RegChunk& rc, const UpdArgs& a, int 
   const bool plus = ci < ncp;
   const int r0 = (plus ? ci : ci - ncp) * G::R;
   const int rows = ci < nch ? min(G::R, (plus ? a.np : a.nm) - r0) : 0;
-  const uint4* src = (const uint4*)(plus ? a.xp : a.xm) + (int64_t)r0 * upr + threadIdx.x;
-  const int cnt = rows * upr - (int)threadIdx.x;
+  const uint4* src = (const uint4*)(plus ? a.xp : a.xm) + (int64_t)r0 * upr;
+  if (rows == G::R) {
+    const int last = G::R * upr - 1;
 #pragma unroll
-  for (int q = 0; q < PREF_UNITS; ++q)
-    rc.u[q] = (256 * q < cnt) ? src[256 * q] : make_uint4(0u, 0u, 0u, 0u);
+    for (int q = 0; q < PREF_UNITS; ++q) rc.u[q] = src[min((int)threadIdx.x + 256 * q, last)];
+  } else {
+    const int cnt = rows * upr - (int)threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < PREF_UNITS; ++q)
+      rc.u[q] = (256 * q < cnt) ? src[threadIdx.x + 256 * q] : make_uint4(0u, 0u, 0u, 0u);
+  }
 }
 
 template <int P, int STR>
@@ -143,21 +172,80 @@ __device__ __forceinline__ void load_chunk_scalar(char* smem, const UpdArgs& a, 
   }
 }
 
+// Direct path: this lane's byte offset, from a wave's first row of a chunk,
+// of the 16-byte unit it copies in each load round (the same for every
+// chunk).  Unit i of a wave's buffer is row i / SU, column unit i % SU; units
+// past a row's data (LDS padding, never read) copy the first unit instead.
+template <int P, int STR> struct DirectLanes {
+  static constexpr int NQ = DirectGeom<P, STR>::WU / 64;
+  uint32_t off[NQ];
+};
+
+template <int P, int STR>
+__device__ __forceinline__ void direct_lanes(DirectLanes<P, STR>& dl, int n) {
+  using G = DirectGeom<P, STR>;
+  const int upr = n * G::ES / 16;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < DirectLanes<P, STR>::NQ; ++q) {
+    const int i = q * 64 + lane;
+    const int r = i / G::SU, c = i - r * G::SU;
+    dl.off[q] = (c < upr && r < G::RW) ? (uint32_t)((r * upr + c) * 16) : 0u;
+  }
+}
+
+// Starts the copy of this wave's rows of chunk `ci` into its buffer at `wbuf`
+// (64 consecutive units per load, lane L at unit 64 q + L).  Rows past the
+// end of the last chunk of a sign copy a 16-byte block of zeros.
+template <int P, int STR>
+__device__ __forceinline__ void issue_chunk(char* wbuf, const UpdArgs& a, const DirectLanes<P, STR>& dl, int ci,
+                                            int ncp, int wave) {
+  using G = DirectGeom<P, STR>;
+  const int upr = a.n * G::ES / 16;
+  const bool plus = ci < ncp;
+  const int r0 = (plus ? ci : ci - ncp) * G::R + wave * G::RW;
+  const int rows = (plus ? a.np : a.nm) - r0;
+  const char* src = (const char*)(plus ? a.xp : a.xm) + (int64_t)r0 * upr * 16;
+  if (rows >= G::RW) {
+#pragma unroll
+    for (int q = 0; q < DirectLanes<P, STR>::NQ; ++q)
+      __builtin_amdgcn_global_load_lds((const void*)(src + dl.off[q]),
+                                       (__attribute__((address_space(3))) void*)(wbuf + q * 1024), 16, 0, 0);
+  } else {
+    const uint32_t lim = rows > 0 ? (uint32_t)(rows * upr * 16) : 0u;
+#pragma unroll
+    for (int q = 0; q < DirectLanes<P, STR>::NQ; ++q) {
+      const char* g = dl.off[q] < lim ? src + dl.off[q] : (const char*)a.zero;
+      __builtin_amdgcn_global_load_lds((const void*)g,
+                                       (__attribute__((address_space(3))) void*)(wbuf + q * 1024), 16, 0, 0);
+    }
+  }
+}
+
 // Row mapping inside a chunk of R rows: wave w owns rows [w R/4, (w+1) R/4).
-// f32/f64 (16x16x4): at its k-step s, lane group q = lane/16 takes row
-// w R/4 + 4 s + q.  bf16 (16x16x32): at k-step s, K index 8 q + j of group q
-// is row w R/4 + 32 s + 4 j + q.  A and B use the same row for the same K
-// index, so the products pair up; the four groups always read four
-// consecutive rows (4 banks apart).
+// f32/f64 (16x16x4), NKS = R/16 k-steps per wave: with NKS even, k-steps 2u
+// and 2u+1 of lane group q = lane/16 take the adjacent rows w R/4 + 8u + 2q
+// and 8u + 2q + 1 (their two loads merge into one two-address LDS read);
+// with NKS odd, k-step s takes row w R/4 + 4s + q.  bf16 (16x16x32): at
+// k-step s, K index 8q + j of group q is row w R/4 + 32s + 4j + q.  A and B
+// use the same row for the same K index, so the products pair up; the four
+// groups always read rows 1 or 2 apart (4 or 8 banks).
+template <int NKS, int STR, int ES>
+__device__ __forceinline__ constexpr int koff(int s) {
+  return (NKS % 2 == 0) ? (8 * (s >> 1) + (s & 1)) * STR * ES : 4 * s * STR * ES;
+}
+
 template <int P, int H, int MR, int TM, int TN, int STR, bool VL>
 __device__ void upd_body(const UpdArgs& a, const UpdItem& it, char* smem) {
   using T = typename Tr<P>::X;
   using Acc = typename Tr<P>::Acc;
   using A1 = typename Tr<P>::A1;
   using G = ChunkGeom<P, STR>;
+  using D = DirectGeom<P, STR>;
   constexpr int KS = Tr<P>::KS;
+  constexpr bool DIRECT = (KS == 4 && VL);
   constexpr int ES = G::ES;
-  constexpr int R = G::R;
+  constexpr int R = DIRECT ? D::R : G::R;
   constexpr int RW = R / 4;
   constexpr int NKS = RW / KS;                 // k-steps per wave per chunk
   constexpr int K_ORD = H + MR;
@@ -166,7 +254,11 @@ __device__ void upd_body(const UpdArgs& a, const UpdItem& it, char* smem) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const LeftCol* __restrict__ left = a.left[K_ORD];
   const RightCol* __restrict__ right = a.right[K_ORD];
-  const int lrow = wave * RW + (lane >> 4);
+  // this lane's first LDS row: in the direct path inside the wave's own
+  // buffer (which starts at byte wave * WU * 16), else inside the chunk
+  const int lgrp = (KS == 4 && NKS % 2 == 0) ? 2 * (lane >> 4) : (lane >> 4);
+  const int lrow = DIRECT ? lgrp : wave * RW + lgrp;
+  const int lbase = DIRECT ? wave * D::WU * 16 : 0;
 
   // Byte addresses of this lane's factor columns at its first row.  Rows past
   // M, columns past N and padded data columns read column 0: their products
@@ -178,19 +270,19 @@ __device__ void upd_body(const UpdArgs& a, const UpdItem& it, char* smem) {
     const int r = min(it.r0 + 16 * f + (lane & 15), it.M - 1);
     const LeftCol L = left[it.lrow0 + r];
 #pragma unroll
-    for (int q = 0; q < H; ++q) ao[f][q] = (lrow * STR + (L.c[q] < a.n ? L.c[q] : 0)) * ES;
+    for (int q = 0; q < H; ++q) ao[f][q] = lbase + (lrow * STR + (L.c[q] < a.n ? L.c[q] : 0)) * ES;
   }
 #pragma unroll
   for (int g = 0; g < TN; ++g) {
     const int c = min(it.c0 + 16 * g + (lane & 15), it.N - 1);
     const RightCol Rc = right[it.rcol0 + c];
 #pragma unroll
-    for (int q = 0; q < MRC; ++q) bo[g][q] = (lrow * STR + ((q < MR && Rc.c[q] < a.n) ? Rc.c[q] : 0)) * ES;
+    for (int q = 0; q < MRC; ++q) bo[g][q] = lbase + (lrow * STR + ((q < MR && Rc.c[q] < a.n) ? Rc.c[q] : 0)) * ES;
   }
   // (every fragment is multiplied, also those past M or N: branching around
   // MFMAs makes the compiler shuffle the accumulators through VGPRs)
   int slot[PREF_UNITS];
-  if constexpr (VL) chunk_slots<P, STR>(slot, a.n);
+  if constexpr (VL && !DIRECT) chunk_slots<P, STR>(slot, a.n);
 
   Acc acc[TM][TN];
 #pragma unroll
@@ -202,9 +294,91 @@ __device__ void upd_body(const UpdArgs& a, const UpdItem& it, char* smem) {
 
   const int ncp = (a.np + R - 1) / R;
   const int nch = ncp + (a.nm + R - 1) / R;
+
+  // k-steps of one chunk held at byte offset BO of smem (f32/f64 paths)
+  auto multiply_chunk = [&](auto bo_c) __attribute__((always_inline)) {
+    constexpr int BO = decltype(bo_c)::value;
+    // f32: the factor values of k-step s+1 are loaded while k-step s
+    // multiplies (f64 loads them just before use: two buffers of doubles
+    // would cost the fourth wave per SIMD)
+    constexpr bool PIPE = (P == PREC_F32);
+    constexpr int NB = PIPE ? 2 : 1;
+    T fa[NB][TM][H], fb[NB][TN][MRC];
+    auto load_factors = [&](int st, int buf) __attribute__((always_inline)) {
+      const int so = koff<NKS, STR, ES>(st) + BO;
+#pragma unroll
+      for (int f = 0; f < TM; ++f)
+#pragma unroll
+        for (int q = 0; q < H; ++q) fa[buf][f][q] = *(const T*)(smem + ao[f][q] + so);
+#pragma unroll
+      for (int g = 0; g < TN; ++g)
+#pragma unroll
+        for (int q = 0; q < MR; ++q) fb[buf][g][q] = *(const T*)(smem + bo[g][q] + so);
+    };
+    load_factors(0, 0);
+#pragma unroll
+    for (int st = 0; st < NKS; ++st) {
+      const int cur = PIPE ? (st & 1) : 0;
+      if (PIPE && st + 1 < NKS) load_factors(st + 1, cur ^ 1);
+      if (!PIPE && st > 0) load_factors(st, 0);
+      T A[TM], B[TN];
+#pragma unroll
+      for (int f = 0; f < TM; ++f) {
+        T v = fa[cur][f][0];
+#pragma unroll
+        for (int q = 1; q < H; ++q) v *= fa[cur][f][q];
+        A[f] = v;
+      }
+#pragma unroll
+      for (int g = 0; g < TN; ++g) {
+        T v = T(1);
+        if constexpr (MR > 0) {
+          v = fb[cur][g][0];
+#pragma unroll
+          for (int q = 1; q < MR; ++q) v *= fb[cur][g][q];
+        }
+        B[g] = v;
+      }
+#pragma unroll
+      for (int f = 0; f < TM; ++f)
+#pragma unroll
+        for (int g = 0; g < TN; ++g) acc[f][g] = mma(A[f], B[g], acc[f][g]);
+    }
+  };
+
+  if constexpr (DIRECT) {
+    // Per wave: wait for this wave's copy of chunk ci (its own loads only),
+    // start the copy of chunk ci+1 into the other buffer (whose reads of
+    // chunk ci-1 have completed), then run the k-steps of chunk ci.
+    DirectLanes<P, STR> dl;
+    direct_lanes<P, STR>(dl, a.n);
+    char* wbuf = smem + wave * D::WU * 16;
+    __syncthreads();  // the previous item's epilogue may still read smem
+    issue_chunk<P, STR>(wbuf, a, dl, 0, ncp, wave);
+    auto run_chunk = [&](int ci) __attribute__((always_inline)) {
+      __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+      if (ci + 1 < nch) issue_chunk<P, STR>(wbuf + ((ci + 1) & 1) * D::BUFB, a, dl, ci + 1, ncp, wave);
+      if (ci & 1) multiply_chunk(IntC<D::BUFB>{});
+      else multiply_chunk(IntC<0>{});
+    };
+    int ci = 0;
+    for (; ci < ncp; ++ci) run_chunk(ci);
+    if (nch > ncp) {
+#pragma unroll
+      for (int f = 0; f < TM; ++f)
+#pragma unroll
+        for (int g = 0; g < TN; ++g) acc[f][g] = -acc[f][g];
+      for (; ci < nch; ++ci) run_chunk(ci);
+#pragma unroll
+      for (int f = 0; f < TM; ++f)
+#pragma unroll
+        for (int g = 0; g < TN; ++g) acc[f][g] = -acc[f][g];
+    }
+  } else {
   RegChunk rc;
   if constexpr (VL) fetch_chunk<P, STR>(rc, a, 0, ncp, nch);
-  for (int ci = 0; ci < nch; ++ci) {
+
+  auto run_chunk = [&](int ci) __attribute__((always_inline)) {
     __syncthreads();
     if constexpr (VL) {
       store_chunk<P, STR>(smem, rc, slot);
@@ -214,50 +388,17 @@ __device__ void upd_body(const UpdArgs& a, const UpdItem& it, char* smem) {
       load_chunk_scalar<P, STR>(smem, a, ci, ncp);
       __syncthreads();
     }
-    // Sign: the minus chunks add their products to the negated accumulators,
-    // acc <- -(-acc + sum_minus) = acc - sum_minus, so no product is negated.
-    if (ci == ncp) {
-#pragma unroll
-      for (int f = 0; f < TM; ++f)
-#pragma unroll
-        for (int g = 0; g < TN; ++g) acc[f][g] = -acc[f][g];
-    }
     if constexpr (KS == 4) {
-#pragma unroll
-      for (int s = 0; s < NKS; ++s) {
-        const int so = 4 * s * STR * ES;
-        T A[TM], B[TN];
-#pragma unroll
-        for (int f = 0; f < TM; ++f) {
-          T v = *(const T*)(smem + ao[f][0] + so);
-#pragma unroll
-          for (int q = 1; q < H; ++q) v *= *(const T*)(smem + ao[f][q] + so);
-          A[f] = v;
-        }
-#pragma unroll
-        for (int g = 0; g < TN; ++g) {
-          T v = T(1);
-          if constexpr (MR > 0) {
-            v = *(const T*)(smem + bo[g][0] + so);
-#pragma unroll
-            for (int q = 1; q < MR; ++q) v *= *(const T*)(smem + bo[g][q] + so);
-          }
-          B[g] = v;
-        }
-#pragma unroll
-        for (int f = 0; f < TM; ++f)
-#pragma unroll
-          for (int g = 0; g < TN; ++g) acc[f][g] = mma(A[f], B[g], acc[f][g]);
-      }
+      multiply_chunk(IntC<0>{});
     } else {
       // split-BF16x3: v = hi + lo with hi = RNE_bf16(v), lo = RNE_bf16(v - hi);
       // a*b ~ ah*bh + ah*bl + al*bh, accumulated in FP32.
 #pragma unroll
-      for (int s = 0; s < NKS; ++s) {
+      for (int st = 0; st < NKS; ++st) {
         bf16x8 Ah[TM], Al[TM], Bh[TN], Bl[TN];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-          const int so = (32 * s + 4 * j) * STR * ES;
+          const int so = (32 * st + 4 * j) * STR * ES;
 #pragma unroll
           for (int f = 0; f < TM; ++f) {
             float v = *(const float*)(smem + ao[f][0] + so);
@@ -290,19 +431,30 @@ __device__ void upd_body(const UpdArgs& a, const UpdItem& it, char* smem) {
           }
       }
     }
-  }
+  };
 
-  if (nch > ncp) {  // undo the negation of the minus phase
+  // Sign: the plus chunks run first; the minus chunks then add their
+  // products to the negated accumulators, acc <- -(-acc + sum_minus), so no
+  // product is negated.
+  int ci = 0;
+  for (; ci < ncp; ++ci) run_chunk(ci);
+  if (nch > ncp) {
+#pragma unroll
+    for (int f = 0; f < TM; ++f)
+#pragma unroll
+      for (int g = 0; g < TN; ++g) acc[f][g] = -acc[f][g];
+    for (; ci < nch; ++ci) run_chunk(ci);
 #pragma unroll
     for (int f = 0; f < TM; ++f)
 #pragma unroll
       for (int g = 0; g < TN; ++g) acc[f][g] = -acc[f][g];
   }
+  }
 
   // Reduce the four waves' partial sums in a fixed order (wave 0 + 1 + 2 + 3),
   // GF fragments at a time through LDS, and fold every stored element.
   constexpr int NF = TM * TN;
-  constexpr int LDSB = R * STR * ES;
+  constexpr int LDSB = DIRECT ? D::SMEM : R * STR * ES;
   constexpr int GMAX = LDSB / (4 * 256 * (int)sizeof(A1));
   constexpr int GF = NF < GMAX ? NF : GMAX;
   static_assert(GF >= 1, "reduction buffer");
@@ -346,21 +498,35 @@ __device__ void upd_body(const UpdArgs& a, const UpdItem& it, char* smem) {
   }
 }
 
-template <int P, int TM, int TN, int STR, bool VL>
-__global__ __launch_bounds__(256) void k_update(UpdArgs a) {
-  using G = ChunkGeom<P, STR>;
-  static_assert(G::R >= G::UB, "chunk smaller than one unit block per wave");
-  __shared__ __attribute__((aligned(16))) char smem[G::R * STR * G::ES];
-  const UpdItem it = a.items[blockIdx.x];
+// LDS bytes of the update kernels: the two direct-path buffers, or the one
+// register-staged chunk.
+template <int P, int STR, bool VL>
+constexpr int upd_smem_bytes() {
+  if constexpr (Tr<P>::KS == 4 && VL) return DirectGeom<P, STR>::SMEM;
+  else return ChunkGeom<P, STR>::R * STR * ChunkGeom<P, STR>::ES;
+}
+
+// One tile of order k (KMAX: the highest order the launch holds; the
+// register allocation follows the largest body compiled in).
+template <int P, int TM, int TN, int STR, bool VL, int KMAX>
+__device__ __forceinline__ void upd_dispatch(const UpdArgs& a, const UpdItem& it, char* smem) {
   switch (it.k) {
     case 1: upd_body<P, 1, 0, TM, TN, STR, VL>(a, it, smem); break;
     case 2: upd_body<P, 1, 1, TM, TN, STR, VL>(a, it, smem); break;
     case 3: upd_body<P, 2, 1, TM, TN, STR, VL>(a, it, smem); break;
     case 4: upd_body<P, 2, 2, TM, TN, STR, VL>(a, it, smem); break;
-    case 5: upd_body<P, 3, 2, TM, TN, STR, VL>(a, it, smem); break;
-    case 6: upd_body<P, 3, 3, TM, TN, STR, VL>(a, it, smem); break;
+    case 5: if constexpr (KMAX >= 5) upd_body<P, 3, 2, TM, TN, STR, VL>(a, it, smem); break;
+    case 6: if constexpr (KMAX >= 6) upd_body<P, 3, 3, TM, TN, STR, VL>(a, it, smem); break;
     default: break;
   }
+}
+
+template <int P, int TM, int TN, int STR, bool VL, int KMAX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_BF16X3 ? 1 : 4))) void k_update(
+    UpdArgs a) {
+  __shared__ __attribute__((aligned(16))) char smem[upd_smem_bytes<P, STR, VL>()];
+  const UpdItem it = a.items[blockIdx.x];
+  upd_dispatch<P, TM, TN, STR, VL, KMAX>(a, it, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -530,33 +696,27 @@ __global__ __launch_bounds__(1024) void k_norms_batch(const NormArgs* __restrict
 // context's arguments (input pointers and row counts refreshed per update),
 // items[] the tiles of all contexts sharing this stride, longest first; every
 // workgroup walks the item list with a grid-sized stride.
-template <int P, int TM, int TN, int STR, bool VL>
-__global__ __launch_bounds__(256) void k_update_batch(const UpdArgs* __restrict__ ctxs,
+template <int P, int TM, int TN, int STR, bool VL, int KMAX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_BF16X3 ? 1 : 4))) void k_update_batch(
+    const UpdArgs* __restrict__ ctxs,
                                                       const UpdItem* __restrict__ items, int nitems) {
-  using G = ChunkGeom<P, STR>;
-  static_assert(G::R >= G::UB, "chunk smaller than one unit block per wave");
-  __shared__ __attribute__((aligned(16))) char smem[G::R * STR * G::ES];
+  __shared__ __attribute__((aligned(16))) char smem[upd_smem_bytes<P, STR, VL>()];
   for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
     const UpdItem it = items[i];
     const UpdArgs a = ctxs[it.ctx];
-    switch (it.k) {
-      case 1: upd_body<P, 1, 0, TM, TN, STR, VL>(a, it, smem); break;
-      case 2: upd_body<P, 1, 1, TM, TN, STR, VL>(a, it, smem); break;
-      case 3: upd_body<P, 2, 1, TM, TN, STR, VL>(a, it, smem); break;
-      case 4: upd_body<P, 2, 2, TM, TN, STR, VL>(a, it, smem); break;
-      case 5: upd_body<P, 3, 2, TM, TN, STR, VL>(a, it, smem); break;
-      case 6: upd_body<P, 3, 3, TM, TN, STR, VL>(a, it, smem); break;
-      default: break;
-    }
+    upd_dispatch<P, TM, TN, STR, VL, KMAX>(a, it, smem);
     __syncthreads();  // the next item reuses the LDS chunk buffer
   }
 }
 
 template <int P, int STR, bool VL>
-static hipError_t launch_batch_one(const UpdArgs* ctxs, const UpdItem* items, int nitems, int grid,
+static hipError_t launch_batch_one(int kmax, const UpdArgs* ctxs, const UpdItem* items, int nitems, int grid,
                                    hipStream_t st) {
   if constexpr (ChunkGeom<P, STR>::R >= ChunkGeom<P, STR>::UB) {
-    hipLaunchKernelGGL((k_update_batch<P, 2, 2, STR, VL>), dim3(grid), dim3(256), 0, st, ctxs, items, nitems);
+    if (kmax <= 4)
+      hipLaunchKernelGGL((k_update_batch<P, 2, 2, STR, VL, 4>), dim3(grid), dim3(256), 0, st, ctxs, items, nitems);
+    else
+      hipLaunchKernelGGL((k_update_batch<P, 2, 2, STR, VL, 6>), dim3(grid), dim3(256), 0, st, ctxs, items, nitems);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -564,64 +724,61 @@ static hipError_t launch_batch_one(const UpdArgs* ctxs, const UpdItem* items, in
 }
 
 template <int P>
-static hipError_t launch_batch_p(int str, bool vl, const UpdArgs* ctxs, const UpdItem* items, int nitems,
-                                 int grid, hipStream_t st) {
+static hipError_t launch_batch_p(int str, bool vl, int kmax, const UpdArgs* ctxs, const UpdItem* items,
+                                 int nitems, int grid, hipStream_t st) {
   switch (str) {
-    case 36: return vl ? launch_batch_one<P, 36, true>(ctxs, items, nitems, grid, st)
-                       : launch_batch_one<P, 36, false>(ctxs, items, nitems, grid, st);
-    case 68: return vl ? launch_batch_one<P, 68, true>(ctxs, items, nitems, grid, st)
-                       : launch_batch_one<P, 68, false>(ctxs, items, nitems, grid, st);
-    case 132: return vl ? launch_batch_one<P, 132, true>(ctxs, items, nitems, grid, st)
-                        : launch_batch_one<P, 132, false>(ctxs, items, nitems, grid, st);
-    case 260: return vl ? launch_batch_one<P, 260, true>(ctxs, items, nitems, grid, st)
-                        : launch_batch_one<P, 260, false>(ctxs, items, nitems, grid, st);
+    case 36: return vl ? launch_batch_one<P, 36, true>(kmax, ctxs, items, nitems, grid, st)
+                       : launch_batch_one<P, 36, false>(kmax, ctxs, items, nitems, grid, st);
+    case 68: return vl ? launch_batch_one<P, 68, true>(kmax, ctxs, items, nitems, grid, st)
+                       : launch_batch_one<P, 68, false>(kmax, ctxs, items, nitems, grid, st);
+    case 132: return vl ? launch_batch_one<P, 132, true>(kmax, ctxs, items, nitems, grid, st)
+                        : launch_batch_one<P, 132, false>(kmax, ctxs, items, nitems, grid, st);
+    case 260: return vl ? launch_batch_one<P, 260, true>(kmax, ctxs, items, nitems, grid, st)
+                        : launch_batch_one<P, 260, false>(kmax, ctxs, items, nitems, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_update_batch(int prec, int str, bool vl, const UpdArgs* ctxs, const UpdItem* items,
+hipError_t launch_update_batch(int prec, int str, bool vl, int kmax, const UpdArgs* ctxs, const UpdItem* items,
                                int nitems, int grid, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
   switch (prec) {
-    case PREC_F64: return launch_batch_p<PREC_F64>(str, vl, ctxs, items, nitems, grid, st);
-    case PREC_F32: return launch_batch_p<PREC_F32>(str, vl, ctxs, items, nitems, grid, st);
-    case PREC_BF16X3: return launch_batch_p<PREC_BF16X3>(str, vl, ctxs, items, nitems, grid, st);
+    case PREC_F64: return launch_batch_p<PREC_F64>(str, vl, kmax, ctxs, items, nitems, grid, st);
+    case PREC_F32: return launch_batch_p<PREC_F32>(str, vl, kmax, ctxs, items, nitems, grid, st);
+    case PREC_BF16X3: return launch_batch_p<PREC_BF16X3>(str, vl, kmax, ctxs, items, nitems, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int P, int TM, int TN, int STR>
-static hipError_t launch_one(const UpdArgs& a, int nitems, hipStream_t st) {
+template <int P, int STR, bool VL>
+static void launch_kmax(int kmax, const UpdArgs& a, int nitems, hipStream_t st) {
+  if (kmax <= 4) hipLaunchKernelGGL((k_update<P, 2, 2, STR, VL, 4>), dim3(nitems), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((k_update<P, 2, 2, STR, VL, 6>), dim3(nitems), dim3(256), 0, st, a);
+}
+
+template <int P, int STR>
+static hipError_t launch_one(int kmax, const UpdArgs& a, int nitems, hipStream_t st) {
   if constexpr (ChunkGeom<P, STR>::R >= ChunkGeom<P, STR>::UB) {
-    if (a.vec) hipLaunchKernelGGL((k_update<P, TM, TN, STR, true>), dim3(nitems), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((k_update<P, TM, TN, STR, false>), dim3(nitems), dim3(256), 0, st, a);
+    if (a.vec) launch_kmax<P, STR, true>(kmax, a, nitems, st);
+    else launch_kmax<P, STR, false>(kmax, a, nitems, st);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
   }
 }
 
-template <int P, int TM, int TN>
-static hipError_t launch_update_s(int str, const UpdArgs& a, int nitems, hipStream_t st) {
+template <int P>
+static hipError_t launch_update_p(int str, int kmax, const UpdArgs& a, int nitems, hipStream_t st) {
   switch (str) {
-    case 36: return launch_one<P, TM, TN, 36>(a, nitems, st);
-    case 68: return launch_one<P, TM, TN, 68>(a, nitems, st);
-    case 132: return launch_one<P, TM, TN, 132>(a, nitems, st);
-    case 260: return launch_one<P, TM, TN, 260>(a, nitems, st);
+    case 36: return launch_one<P, 36>(kmax, a, nitems, st);
+    case 68: return launch_one<P, 68>(kmax, a, nitems, st);
+    case 132: return launch_one<P, 132>(kmax, a, nitems, st);
+    case 260: return launch_one<P, 260>(kmax, a, nitems, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int P>
-static hipError_t launch_update_p(int tm, int tn, int str, const UpdArgs& a, int nitems, hipStream_t st) {
-  if (tm == 2 && tn == 2) return launch_update_s<P, 2, 2>(str, a, nitems, st);
-  if (tm == 4 && tn == 4) return launch_update_s<P, 4, 4>(str, a, nitems, st);
-  return hipErrorInvalidValue;
-}
-
-bool update_tile_supported(int tm, int tn) {
-  return (tm == 2 && tn == 2) || (tm == 4 && tn == 4);
-}
+bool update_tile_supported(int tm, int tn) { return tm == 2 && tn == 2; }
 
 int update_lds_stride(int n) {
   return n <= 32 ? 36 : n <= 64 ? 68 : n <= 128 ? 132 : n <= 256 ? 260 : 0;
@@ -642,13 +799,14 @@ int update_chunk_rows(int prec, int str) {
   }
 }
 
-hipError_t launch_update(int prec, int tm, int tn, const UpdArgs& a, int nitems, hipStream_t st) {
+hipError_t launch_update(int prec, int tm, int tn, int kmax, const UpdArgs& a, int nitems, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
+  if (!update_tile_supported(tm, tn) || kmax < 1 || kmax > 6) return hipErrorInvalidValue;
   const int str = update_lds_stride(a.n);
   switch (prec) {
-    case PREC_F64: return launch_update_p<PREC_F64>(tm, tn, str, a, nitems, st);
-    case PREC_F32: return launch_update_p<PREC_F32>(tm, tn, str, a, nitems, st);
-    case PREC_BF16X3: return launch_update_p<PREC_BF16X3>(tm, tn, str, a, nitems, st);
+    case PREC_F64: return launch_update_p<PREC_F64>(str, kmax, a, nitems, st);
+    case PREC_F32: return launch_update_p<PREC_F32>(str, kmax, a, nitems, st);
+    case PREC_BF16X3: return launch_update_p<PREC_BF16X3>(str, kmax, a, nitems, st);
     default: return hipErrorInvalidValue;
   }
 }
