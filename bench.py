@@ -97,22 +97,28 @@ def sampled_error(ctx, window: np.ndarray, rng, count: int = 40):
     return worst
 
 
-def run_path(prec, s, warmup, steps, check):
+def run_path(path, s, warmup, steps, check):
+    """path: a precision (sliding mode: the new and the leaving rows are both
+    contracted) or '<precision>-fifo' (the batch-increment queue)."""
     import torch
 
     import paper_1701_06446_amd as cum
 
+    prec, _, mode = path.partition("-")
     dt = np.float64 if prec == "fp64" else np.float32
     rows = np.ascontiguousarray(s.rows.astype(dt))
     dev = torch.from_numpy(rows).to("cuda")
-    ctx = cum.cum_init(N, D, B, dev[:T], prec=prec)
+    if mode == "fifo":
+        ctx = cum.cum_init_fifo(N, D, B, dev[:T], P, prec=prec)
+    else:
+        ctx = cum.cum_init(N, D, B, dev[:T], prec=prec)
     w = 0
 
     def step():
         nonlocal w
         w += 1
         lo, hi = (w - 1) * P, w * P
-        cum.cum_update(ctx, dev[T + lo:T + hi], dev[lo:hi])
+        cum.cum_update(ctx, dev[T + lo:T + hi], None if mode == "fifo" else dev[lo:hi])
 
     for _ in range(warmup):
         step()
@@ -152,6 +158,8 @@ def run_path(prec, s, warmup, steps, check):
         window = rows[w * P: w * P + T].astype(np.float64)
         out["err_sampled"] = sampled_error(ctx, window, np.random.default_rng(7))
         out["tol"] = TOL[prec]
+    if mode == "fifo":
+        out["fifo_slots"] = T // P
     cum.cum_free(ctx)
     del dev
     torch.cuda.empty_cache()
@@ -250,7 +258,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16x3"])
-    ap.add_argument("--paths", default="fp64,fp32,bf16x3", help="precisions to measure")
+    ap.add_argument("--paths", default="fp64,fp32,bf16x3,fp32-fifo,bf16x3-fifo",
+                    help="paths to measure: a precision (sliding mode) or <precision>-fifo")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB three times (for scaling HBM counters)")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle check")
@@ -275,6 +284,10 @@ def main():
               file=sys.stderr, flush=True)
         res[prec] = run_path(prec, s, args.warmup, args.steps, not args.no_check)
         print("[bench] path %s: %.3f ms/step" % (prec, res[prec]["ms_per_step"]), file=sys.stderr, flush=True)
+    for path, r in res.items():
+        rows_contracted = P if path.endswith("-fifo") else 2 * P
+        f = algorithmic_flops_per_update(P) * rows_contracted / (2 * P)
+        r["update_kernel_tflops"] = f / (r["kernel_ms"]["update"] * 1e-3) / 1e12
     main = res[args.prec]
     flops = algorithmic_flops_per_update(P)
     upd_ms = main["kernel_ms"]["update"]

@@ -75,9 +75,9 @@ typedef enum {
 
 /*
  * cum_init -- create a context and compute the moments M_1..M_d of the first
- * window X (t x n, row-major), then its cumulants C_1..C_d and norms (Alg. 1,
- * lines "Input"/"Calculate moments").  The window is contracted in chunks of
- * at most 2048 rows, each folded into the compensated running sums.
+ * window X (t x n, row-major), then its cumulants C_1..C_d and norms (the
+ * start of Alg. 1).  The window is contracted in chunks of at most 2048
+ * rows, each folded into the compensated running sums.
  *   ctx        out: the new context (set to NULL on error)
  *   n, d, b    columns (1..255), maximal order (1..6), block size
  *              (1..n; b need not divide n: columns are zero-padded to
@@ -101,6 +101,25 @@ int cum_init(cum_ctx **ctx, int n, int d, int b, const void *X, int64_t t, int p
  *   p      0 <= p <= t; p == 0 is a no-op
  */
 int cum_update(cum_ctx *ctx, const void *X_new, const void *X_old, int64_t p);
+
+/*
+ * cum_init_fifo -- like cum_init, but the context keeps the FIFO of batch
+ * moments that Sec. 3.1 describes as the alternative to contracting the rows
+ * that leave the window: the window is cut into t/p batches of p rows
+ * (oldest first), and the increment sum_{batch} x^(k) of every batch is kept
+ * per stored element (t/p slots per order: FP64 on the CUM_FP64 path, else
+ * FP32, i.e. t/p * cum_num_elems * 4 or 8 bytes per order).  On such a
+ * context cum_update contracts only X_new (half the multiply-adds), folds
+ * its increment into the running sums, folds out the stored increment of
+ * the batch leaving the window (bit-for-bit the value once added, so the
+ * sums do not drift), and stores the new one in its slot.  X_old is not
+ * read (may be NULL) and p must equal the context's batch size; otherwise
+ * CUM_EINVAL.
+ *   p      batch size: 1 <= p <= 2048 (CUM_ESIZE beyond) and t % p == 0
+ *          (CUM_EINVAL otherwise); other arguments as for cum_init
+ */
+int cum_init_fifo(cum_ctx **ctx, int n, int d, int b, const void *X, int64_t t, int64_t p, int prec,
+                  void *hip_stream);
 
 /*
  * cum_get -- copy the order-k cumulant pyramid C_k (k = 1..d, FP64, layout
@@ -179,8 +198,10 @@ const char *cum_last_error(void);
  * cum_batch_update(bt, X_new[m], X_old[m], p[m]) slides member i by p[i]
  * rows (0 <= p[i] <= min(t_i, 2048)); every pointer must be device memory
  * (16-byte aligned when n*sizeof(element) is a multiple of 16) and stay
- * unchanged until the work completes (cum_batch_sync).  CUM_EINVAL on any
- * violation, before any work is queued.
+ * unchanged until the work completes (cum_batch_sync).  A member made by
+ * cum_init_fifo takes p[i] equal to its batch size (or 0) and its X_old[i]
+ * is not read (may be NULL).  CUM_EINVAL on any violation, before any work
+ * is queued.
  */
 typedef struct cum_batch cum_batch;
 int cum_batch_create(cum_batch **batch, cum_ctx *const *ctxs, int m);

@@ -33,7 +33,8 @@ EXPORTS = ("cum_init", "cum_update", "cum_get", "cum_get_moments", "cum_norms",
            "cum_norms_device", "cum_sync", "cum_free", "cum_num_blocks", "cum_num_elems",
            "cum_strerror", "cum_last_error", "cum_plan_coverage", "cum_plan_items",
            "cum_profile_enable", "cum_profile_read", "cum_batch_create", "cum_batch_update",
-           "cum_batch_sync", "cum_batch_free", "cum_loss_grad")
+           "cum_batch_sync", "cum_batch_free", "cum_loss_grad",
+           "cum_init_fifo")
 
 
 class CumError(RuntimeError):
@@ -71,6 +72,7 @@ def _load():
         "cum_batch_update": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64)]),
         "cum_batch_sync": (i32, [vp]),
         "cum_batch_free": (i32, [vp]),
+        "cum_init_fifo": (i32, [ctypes.POINTER(vp), i32, i32, i32, vp, i64, i64, i32, vp]),
         "cum_loss_grad": (i32, [i32, i32, i32, vp, i64, vp, ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_double), vp, vp, vp]),
         "cum_profile_read": (i32, [vp, ctypes.POINTER(i64), pd]),
@@ -122,8 +124,9 @@ def _pointer(X, prec: int, ncols: int):
 class Context:
     """Owns one ``cum_ctx``; released by ``cum_free`` (or garbage collection)."""
 
-    def __init__(self, handle, n, d, b, t, prec):
+    def __init__(self, handle, n, d, b, t, prec, fifo_p=0):
         self.handle, self.n, self.d, self.b, self.t, self.prec = handle, n, d, b, t, prec
+        self.fifo_p = fifo_p
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
@@ -141,12 +144,27 @@ def cum_init(n: int, d: int, b: int, X, prec="fp32", stream=None) -> Context:
     return Context(h, n, d, b, t, p)
 
 
-def cum_update(ctx: Context, X_new, X_old):
-    """Slide the window: X_new enters, X_old (the p oldest rows) leaves."""
+def cum_init_fifo(n: int, d: int, b: int, X, p: int, prec="fp32", stream=None) -> Context:
+    """Like cum_init, keeping the FIFO of the t/p batch increments of the
+    window (updates then contract only the new rows; X_old is not needed)."""
+    pr = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+    addr, t, _keep = _pointer(X, pr, n)
+    h = ctypes.c_void_p()
+    st = None if stream is None else ctypes.c_void_p(int(stream))
+    _check(_lib.cum_init_fifo(ctypes.byref(h), n, d, b, addr, t, p, pr, st), "cum_init_fifo")
+    return Context(h, n, d, b, t, pr, fifo_p=p)
+
+
+def cum_update(ctx: Context, X_new, X_old=None):
+    """Slide the window: X_new enters, X_old (the p oldest rows) leaves.
+    On a FIFO context X_old is not read and may be None."""
     an, pn, _k1 = _pointer(X_new, ctx.prec, ctx.n)
-    ao, po, _k2 = _pointer(X_old, ctx.prec, ctx.n)
-    if pn != po:
-        raise ValueError("X_new and X_old must have the same number of rows")
+    if X_old is None:
+        ao = None
+    else:
+        ao, po, _k2 = _pointer(X_old, ctx.prec, ctx.n)
+        if pn != po:
+            raise ValueError("X_new and X_old must have the same number of rows")
     _check(_lib.cum_update(ctx.handle, an, ao, pn), "cum_update")
 
 
@@ -267,9 +285,12 @@ def cum_batch_update(batch: Batch, X_new, X_old):
     keep = []
     for i, c in enumerate(batch.ctxs):
         an, rn, k1 = _pointer(X_new[i], c.prec, c.n)
-        ao, ro, k2 = _pointer(X_old[i], c.prec, c.n)
-        if rn != ro:
-            raise ValueError("X_new and X_old must have the same number of rows")
+        if X_old[i] is None:
+            ao, k2 = None, None
+        else:
+            ao, ro, k2 = _pointer(X_old[i], c.prec, c.n)
+            if rn != ro:
+                raise ValueError("X_new and X_old must have the same number of rows")
         pn[i], po[i], pp[i] = an, ao, rn
         keep += [k1, k2]
     _check(_lib.cum_batch_update(batch.handle, pn, po, pp), "cum_batch_update")

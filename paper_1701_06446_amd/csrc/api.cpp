@@ -59,6 +59,11 @@ struct cum_ctx {
   // optional per-kernel timing: (class, start, stop) per launch of the
   // classes in profile_mask; events are recycled through a pool
   void* zero = nullptr;  // UPD_ZERO_BYTES zeros: padding source of the update's direct loads
+  // FIFO mode (fifo_p > 0): fifo_q = t / fifo_p slots of batch increments
+  // per order, slot fifo_head holding the oldest batch of the window
+  int64_t fifo_p = 0;
+  int fifo_q = 0, fifo_head = 0;
+  void* snap[CUM_MAXD + 1] = {};
   int profile_mask = 0;
   struct Ev { int cls; hipEvent_t a, b; };
   std::vector<Ev> events;
@@ -214,8 +219,17 @@ UpdArgs base_args(cum_ctx* c) {
   return a;
 }
 
-int run_contraction(cum_ctx* c, const char* xp, int64_t np, const char* xm, int64_t nm) {
+// FIFO arguments of one update: mode (0 off, 1 store, 2 replace) and slot.
+void set_fifo(const cum_ctx* c, UpdArgs& a, int mode, int slot) {
+  a.fifo = mode;
+  for (int k = 1; k <= c->d; ++k)
+    a.snap[k] = mode ? (char*)c->snap[k] + (size_t)slot * (size_t)c->T.ord[k].nelems * c->st_size : nullptr;
+}
+
+int run_contraction(cum_ctx* c, const char* xp, int64_t np, const char* xm, int64_t nm, int fifo = 0,
+                    int slot = 0) {
   UpdArgs a = base_args(c);
+  set_fifo(c, a, fifo, slot);
   const int64_t rows = np > nm ? np : nm;
   const size_t rb = (size_t)c->n * c->x_size;
   for (int64_t q0 = 0; q0 < rows; q0 += kRowChunk) {
@@ -331,7 +345,10 @@ int64_t cum_plan_items(int n, int d, int b) {
   return (int64_t)build_items(T, 1, d, 32, 32).size();
 }
 
-int cum_init(cum_ctx** out, int n, int d, int b, const void* X, int64_t t, int prec,
+namespace {
+
+// Shared by cum_init and cum_init_fifo (fifo_p = 0: plain sliding mode).
+int init_ctx(cum_ctx** out, int n, int d, int b, const void* X, int64_t t, int64_t fifo_p, int prec,
              void* hip_stream) {
   if (!out) return CUM_EINVAL;
   *out = nullptr;
@@ -339,10 +356,14 @@ int cum_init(cum_ctx** out, int n, int d, int b, const void* X, int64_t t, int p
   if (rc != CUM_OK) return rc;
   if (prec != CUM_FP64 && prec != CUM_FP32 && prec != CUM_BF16X3) return CUM_EINVAL;
   if (!X || t < 1 || t > ((int64_t)1 << 40)) return CUM_EINVAL;
+  if (fifo_p < 0 || (fifo_p > 0 && (t % fifo_p != 0))) return CUM_EINVAL;
+  if (fifo_p > kRowChunk || t / (fifo_p ? fifo_p : 1) > (1 << 30)) return CUM_ESIZE;
 
   cum_ctx* c = new (std::nothrow) cum_ctx();
   if (!c) return CUM_ENOMEM;
   c->n = n; c->d = d; c->b = b; c->prec = prec; c->t = t;
+  c->fifo_p = fifo_p;
+  c->fifo_q = fifo_p ? (int)(t / fifo_p) : 0;
   c->stream = (hipStream_t)hip_stream;
   c->x_size = (prec == CUM_FP64) ? 8 : 4;
   c->st_size = (prec == CUM_FP64) ? 8 : 4;
@@ -377,6 +398,9 @@ int cum_init(cum_ctx** out, int n, int d, int b, const void* X, int64_t t, int p
     if ((e = upload(c, &c->right[k], c->T.right[k], &used)) != hipSuccess) return fail(e);
     if ((e = hipMemsetAsync(c->s_hi[k], 0, (size_t)o.nelems * c->st_size, c->stream)) != hipSuccess) return fail(e);
     if ((e = hipMemsetAsync(c->s_lo[k], 0, (size_t)o.nelems * c->st_size, c->stream)) != hipSuccess) return fail(e);
+    if (c->fifo_q &&
+        (e = dalloc(c, &c->snap[k], (size_t)c->fifo_q * (size_t)o.nelems * c->st_size, &used)) != hipSuccess)
+      return fail(e);
   }
   if ((e = upload(c, &c->items, items, &used)) != hipSuccess) return fail(e);
   if ((e = dalloc(c, (void**)&c->norms, (size_t)2 * (d + 1) * 8, &used)) != hipSuccess) return fail(e);
@@ -392,7 +416,14 @@ int cum_init(cum_ctx** out, int n, int d, int b, const void* X, int64_t t, int p
     if ((e = hipMemcpyAsync(tmp, X, wbytes, hipMemcpyHostToDevice, c->stream)) != hipSuccess) return fail(e);
     xw = (const char*)tmp;
   }
-  rc = run_contraction(c, xw, t, nullptr, 0);
+  if (c->fifo_q) {
+    // the window as t / p batches, oldest first: slot q holds batch q
+    const size_t bb = (size_t)fifo_p * n * c->x_size;
+    for (int q = 0; q < c->fifo_q && rc == CUM_OK; ++q)
+      rc = run_contraction(c, xw + (size_t)q * bb, fifo_p, nullptr, 0, 1, q);
+  } else {
+    rc = run_contraction(c, xw, t, nullptr, 0);
+  }
   if (rc == CUM_OK) rc = run_combine_and_norms(c);
   if (rc == CUM_OK && (e = hipStreamSynchronize(c->stream)) != hipSuccess) {
     CUM_NOTE(e, "hipStreamSynchronize after init");
@@ -414,16 +445,30 @@ int cum_init(cum_ctx** out, int n, int d, int b, const void* X, int64_t t, int p
   return CUM_OK;
 }
 
+}  // namespace
+
+int cum_init(cum_ctx** out, int n, int d, int b, const void* X, int64_t t, int prec, void* hip_stream) {
+  return init_ctx(out, n, d, b, X, t, 0, prec, hip_stream);
+}
+
+int cum_init_fifo(cum_ctx** out, int n, int d, int b, const void* X, int64_t t, int64_t p, int prec,
+                  void* hip_stream) {
+  if (p < 1) return CUM_EINVAL;
+  return init_ctx(out, n, d, b, X, t, p, prec, hip_stream);
+}
+
 int cum_update(cum_ctx* c, const void* X_new, const void* X_old, int64_t p) {
   if (!c) return CUM_EINVAL;
   if (!c->ready) return CUM_ESTATE;
   if (p < 0 || p > c->t) return CUM_EINVAL;
   if (p == 0) return CUM_OK;
-  if (!X_new || !X_old) return CUM_EINVAL;
+  const bool fifo = c->fifo_q > 0;
+  if (fifo && p != c->fifo_p) return CUM_EINVAL;
+  if (!X_new || (!fifo && !X_old)) return CUM_EINVAL;
   const char* xn = (const char*)X_new;
-  const char* xo = (const char*)X_old;
+  const char* xo = fifo ? nullptr : (const char*)X_old;
   const size_t bytes = (size_t)p * c->n * c->x_size;
-  const bool dn = is_device_ptr(X_new), dob = is_device_ptr(X_old);
+  const bool dn = is_device_ptr(X_new), dob = fifo || is_device_ptr(X_old);
   if (!dn || !dob) {
     int rc = ensure_stage(c, 2 * bytes);
     if (rc != CUM_OK) return rc;
@@ -443,8 +488,15 @@ int cum_update(cum_ctx* c, const void* X_new, const void* X_old, int64_t p) {
     CUM_TRY(hipStreamWaitEvent(c->stream, c->batch_done, 0));
     c->direct_since_batch = true;
   }
-  int rc = run_contraction(c, xn, p, xo, p);
-  if (rc != CUM_OK) return rc;
+  int rc;
+  if (fifo) {
+    rc = run_contraction(c, xn, p, nullptr, 0, 2, c->fifo_head);
+    if (rc != CUM_OK) return rc;
+    c->fifo_head = (c->fifo_head + 1) % c->fifo_q;
+  } else {
+    rc = run_contraction(c, xn, p, xo, p);
+    if (rc != CUM_OK) return rc;
+  }
   return run_combine_and_norms(c);
 }
 
@@ -754,11 +806,14 @@ int cum_batch_update(cum_batch* bt, const void* const* X_new, const void* const*
     cum_ctx* c = bt->ctx[(size_t)i];
     const int64_t pi = p[i];
     if (pi < 0 || pi > c->t || pi > kRowChunk) return CUM_EINVAL;
+    const bool fifo = c->fifo_q > 0;
+    if (fifo && pi != 0 && pi != c->fifo_p) return CUM_EINVAL;
     if (pi > 0) {
-      if (!X_new[i] || !X_old[i]) return CUM_EINVAL;
-      if (!is_device_ptr(X_new[i]) || !is_device_ptr(X_old[i])) return CUM_EINVAL;
+      const void* xo = fifo ? X_new[i] : X_old[i];
+      if (!X_new[i] || !xo) return CUM_EINVAL;
+      if (!is_device_ptr(X_new[i]) || !is_device_ptr(xo)) return CUM_EINVAL;
       const bool vl = (c->n * (int)c->x_size) % 16 == 0;
-      if (vl && (((uintptr_t)X_new[i] | (uintptr_t)X_old[i]) % 16)) return CUM_EINVAL;
+      if (vl && (((uintptr_t)X_new[i] | (uintptr_t)xo) % 16)) return CUM_EINVAL;
     }
   }
   for (cum_ctx* c : bt->ctx)
@@ -767,18 +822,25 @@ int cum_batch_update(cum_batch* bt, const void* const* X_new, const void* const*
       c->direct_since_batch = false;
     }
   for (int i = 0; i < m; ++i) {
+    cum_ctx* c = bt->ctx[(size_t)i];
     UpdArgs& a = bt->h_upd[(size_t)i];
+    const bool fifo = c->fifo_q > 0 && p[i] > 0;
     a.xp = p[i] ? X_new[i] : nullptr;
-    a.xm = p[i] ? X_old[i] : nullptr;
+    a.xm = (p[i] && !fifo) ? X_old[i] : nullptr;
     a.np = (int)p[i];
-    a.nm = (int)p[i];
-    a.vec = (bt->ctx[(size_t)i]->n * (int)bt->ctx[(size_t)i]->x_size) % 16 == 0;
+    a.nm = fifo ? 0 : (int)p[i];
+    a.vec = (c->n * (int)c->x_size) % 16 == 0;
+    set_fifo(c, a, fifo ? 2 : 0, c->fifo_head);
   }
   // pageable source: the copy is staged before the call returns
   CUM_TRY(hipMemcpyAsync(bt->d_upd, bt->h_upd.data(), bt->h_upd.size() * sizeof(UpdArgs), hipMemcpyHostToDevice,
                          bt->stream));
   CUM_TRY(hipGraphLaunch(bt->exec, bt->stream));
   CUM_TRY(hipEventRecord(bt->done, bt->stream));
+  for (int i = 0; i < m; ++i) {
+    cum_ctx* c = bt->ctx[(size_t)i];
+    if (c->fifo_q > 0 && p[i] > 0) c->fifo_head = (c->fifo_head + 1) % c->fifo_q;
+  }
   return CUM_OK;
 }
 

@@ -28,6 +28,10 @@ struct UpdArgs {
   const RightCol* right[CUM_MAXD + 1];
   void* s_hi[CUM_MAXD + 1]; // running window sums, compensated pair
   void* s_lo[CUM_MAXD + 1];
+  // FIFO of batch increments: 0 off; 1 fold the increment and store it in
+  // snap; 2 fold the increment, fold out the one stored in snap, store it
+  int fifo;
+  void* snap[CUM_MAXD + 1]; // this update's FIFO slot, one value per stored element
 };
 
 // LDS budget for a combine block's staged lower-order sub-blocks.

@@ -492,6 +492,12 @@ __device__ void upd_body(const UpdArgs& a, const UpdItem& it, char* smem) {
           const A1 sum = ((red[e] + red[GF * 256 + e]) + red[2 * GF * 256 + e]) + red[3 * GF * 256 + e];
           const int64_t off = L.base + Rc.base;
           fold<A1>(shi + off, slo + off, sum);
+          if (a.fifo) {
+            // the batch leaving the window: its increment, exactly as it was added
+            A1* sp = (A1*)a.snap[K_ORD] + off;
+            if (a.fifo == 2) fold<A1>(shi + off, slo + off, -*sp);
+            *sp = sum;
+          }
         }
       }
     }
