@@ -167,6 +167,25 @@ int cum_profile_enable(cum_ctx *ctx, int on);
  */
 int cum_profile_read(cum_ctx *ctx, int64_t *launches, double *total_ms);
 
+/*
+ * cum_set_combine -- how the moment -> cumulant combine forms each element
+ * (takes effect at the next cum_update):
+ *   CUM_COMBINE_PARTITIONS  Alg. 4: c_I = m_I minus, over every partition of
+ *                           I's positions into 2..|I| parts, the product of
+ *                           the parts' cumulants (B(|I|) - 1 terms; default)
+ *   CUM_COMBINE_RECURSION   c_I = m_I minus, over the proper subsets B that
+ *                           hold I's first position, c_B * m_{I\B}
+ *                           (2^(|I|-1) - 1 terms: the moment-cumulant
+ *                           relation grouped by the part that holds the first
+ *                           position; the same value up to FP64 rounding)
+ * The recursion runs in the fused combine, which stages each order-d block's
+ * lower-order sub-blocks in 64 KB of LDS: CUM_ESIZE when
+ * ((b+1)^d - 1 - b^d) * 16 bytes exceed that (e.g. d = 6 with b = 4).  A
+ * batch (below) uses each member's method as set when the batch was created.
+ */
+enum { CUM_COMBINE_PARTITIONS = 0, CUM_COMBINE_RECURSION = 1 };
+int cum_set_combine(cum_ctx *ctx, int method);
+
 /* cum_sync -- wait for all work queued on the context's stream. */
 int cum_sync(cum_ctx *ctx);
 

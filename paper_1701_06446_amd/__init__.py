@@ -34,7 +34,7 @@ EXPORTS = ("cum_init", "cum_update", "cum_get", "cum_get_moments", "cum_norms",
            "cum_strerror", "cum_last_error", "cum_plan_coverage", "cum_plan_items",
            "cum_profile_enable", "cum_profile_read", "cum_batch_create", "cum_batch_update",
            "cum_batch_sync", "cum_batch_free", "cum_loss_grad",
-           "cum_init_fifo")
+           "cum_init_fifo", "cum_set_combine")
 
 
 class CumError(RuntimeError):
@@ -72,6 +72,7 @@ def _load():
         "cum_batch_update": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64)]),
         "cum_batch_sync": (i32, [vp]),
         "cum_batch_free": (i32, [vp]),
+        "cum_set_combine": (i32, [vp, i32]),
         "cum_init_fifo": (i32, [ctypes.POINTER(vp), i32, i32, i32, vp, i64, i64, i32, vp]),
         "cum_loss_grad": (i32, [i32, i32, i32, vp, i64, vp, ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_double), vp, vp, vp]),
@@ -153,6 +154,16 @@ def cum_init_fifo(n: int, d: int, b: int, X, p: int, prec="fp32", stream=None) -
     st = None if stream is None else ctypes.c_void_p(int(stream))
     _check(_lib.cum_init_fifo(ctypes.byref(h), n, d, b, addr, t, p, pr, st), "cum_init_fifo")
     return Context(h, n, d, b, t, pr, fifo_p=p)
+
+
+COMBINE = {"partitions": 0, "recursion": 1}
+
+
+def cum_set_combine(ctx: Context, method="partitions"):
+    """'partitions' (Alg. 4, default) or 'recursion' (c_I = m_I - sum over B
+    holding I's first position of c_B m_{I\\B}); from the next update on."""
+    _check(_lib.cum_set_combine(ctx.handle, COMBINE[method] if isinstance(method, str) else int(method)),
+           "cum_set_combine")
 
 
 def cum_update(ctx: Context, X_new, X_old=None):

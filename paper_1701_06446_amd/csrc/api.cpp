@@ -64,6 +64,12 @@ struct cum_ctx {
   int64_t fifo_p = 0;
   int fifo_q = 0, fifo_head = 0;
   void* snap[CUM_MAXD + 1] = {};
+  // fused combine over each order-d block's sub-block lattice (lat_lds > 0
+  // when it fits in LDS): designation bits per order-d block, LDS offsets
+  uint8_t* desig = nullptr;
+  size_t lat_lds = 0;
+  int lat_off[(1 << CUM_MAXD) + 1] = {};
+  int combine = CUM_COMBINE_PARTITIONS;
   int profile_mask = 0;
   struct Ev { int cls; hipEvent_t a, b; };
   std::vector<Ev> events;
@@ -246,8 +252,33 @@ int run_contraction(cum_ctx* c, const char* xp, int64_t np, const char* xm, int6
   return CUM_OK;
 }
 
+LatArgs lat_args(const cum_ctx* c) {
+  LatArgs la{};
+  la.b = c->b;
+  la.log2b = ((c->b & (c->b - 1)) == 0) ? __builtin_ctz((unsigned)c->b) : -1;
+  la.subrank = c->subrank[c->d];
+  la.desig = c->desig;
+  la.inv_t = 1.0 / (double)c->t;
+  for (int k = 1; k <= c->d; ++k) {
+    la.s_hi[k] = c->s_hi[k];
+    la.s_lo[k] = c->s_lo[k];
+    la.C[k] = c->C[k];
+    la.mult[k] = c->mult[k];
+    la.partial[k] = c->partial[k];
+  }
+  for (int m = 0; m <= (1 << c->d); ++m) la.off[m] = c->lat_off[m];
+  la.rec = c->combine == CUM_COMBINE_RECURSION;
+  return la;
+}
+
 int run_combine_and_norms(cum_ctx* c) {
-  for (int s = 1; s <= c->d; ++s) {
+  if (c->lat_lds > 0) {
+    const LatArgs la = lat_args(c);
+    Timed tm(c, 1);
+    CUM_TRY(launch_combine_lattice(c->prec, c->d, c->combine == CUM_COMBINE_RECURSION, la,
+                                   c->T.ord[c->d].nblocks, c->lat_lds, c->stream));
+  }
+  for (int s = 1; s <= c->d && c->lat_lds == 0; ++s) {
     CombArgs a{};
     a.b = c->b;
     a.nbar = c->T.nbar;
@@ -405,6 +436,31 @@ int init_ctx(cum_ctx** out, int n, int d, int b, const void* X, int64_t t, int64
   if ((e = upload(c, &c->items, items, &used)) != hipSuccess) return fail(e);
   if ((e = dalloc(c, (void**)&c->norms, (size_t)2 * (d + 1) * 8, &used)) != hipSuccess) return fail(e);
   if ((e = dalloc(c, &c->zero, UPD_ZERO_BYTES, &used)) != hipSuccess) return fail(e);
+  if (lattice_lds_bytes(d, b) <= LAT_LDS_BYTES) {
+    // order-d block j writes its prefix-s block when j_s = ... = j_d
+    const OrderInfo& od = c->T.ord[d];
+    std::vector<uint8_t> des((size_t)od.nblocks, 0);
+    for (int64_t r = 0; r < od.nblocks; ++r) {
+      const uint8_t* tu = &c->T.tuples[d][(size_t)r * d];
+      for (int q = 1; q < d; ++q) {
+        bool tail = true;
+        for (int u = q; u < d; ++u) tail = tail && tu[u] == tu[q - 1];
+        if (tail) des[(size_t)r] |= (uint8_t)(1 << q);
+      }
+    }
+    if ((e = upload(c, &c->desig, des, &used)) != hipSuccess) return fail(e);
+    int off = 0;
+    for (int m = 1; m < (1 << d) - 1; ++m) {
+      c->lat_off[m] = off;
+      int bl = 1;
+      for (int q = 0; q < __builtin_popcount(m); ++q) bl *= b;
+      off += bl;
+    }
+    c->lat_off[(1 << d) - 1] = off;
+    c->lat_off[1 << d] = off;
+    c->lat_lds = lattice_lds_bytes(d, b);
+    if (c->lat_lds == 0) c->lat_lds = 16;  // d = 1: no sub-blocks
+  }
   if ((e = hipMemsetAsync(c->zero, 0, UPD_ZERO_BYTES, c->stream)) != hipSuccess) return fail(e);
 
   // the window, on the device
@@ -589,6 +645,15 @@ int cum_profile_read(cum_ctx* c, int64_t* launches, double* total_ms) {
   return CUM_OK;
 }
 
+int cum_set_combine(cum_ctx* c, int method) {
+  if (!c) return CUM_EINVAL;
+  if (!c->ready) return CUM_ESTATE;
+  if (method != CUM_COMBINE_PARTITIONS && method != CUM_COMBINE_RECURSION) return CUM_EINVAL;
+  if (method == CUM_COMBINE_RECURSION && c->lat_lds == 0) return CUM_ESIZE;
+  c->combine = method;
+  return CUM_OK;
+}
+
 int cum_free(cum_ctx* c) {
   if (!c) return CUM_OK;
   if (c->ready) (void)wait_batch(c);
@@ -621,6 +686,12 @@ struct cum_batch {
   int comb_grid[CUM_MAXD + 1] = {};
   size_t stage_bytes[CUM_MAXD + 1] = {};
   NormArgs* d_norm = nullptr;
+  // fused combine of the members whose lattices fit, one launch per order d
+  LatArgs* d_lat = nullptr;
+  int64_t* lat_items[CUM_MAXD + 1] = {};
+  int nlat[CUM_MAXD + 1] = {};
+  int lat_grid[CUM_MAXD + 1] = {};
+  size_t lat_lds[CUM_MAXD + 1] = {};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipEvent_t done = nullptr;
@@ -654,6 +725,9 @@ hipError_t bupload(cum_batch* bt, V** dst, const V* src, size_t count) {
 int batch_launch_all(cum_batch* bt) {
   for (const auto& g : bt->groups)
     CUM_TRY(launch_update_batch(bt->prec, g.str, g.vl, g.kmax, bt->d_upd, g.items, g.nitems, g.grid, bt->stream));
+  for (int s = 1; s <= CUM_MAXD; ++s)
+    CUM_TRY(launch_combine_lattice_batch(bt->prec, s, bt->d_lat, bt->lat_items[s], bt->nlat[s], bt->lat_grid[s],
+                                         bt->lat_lds[s], bt->stream));
   for (int s = 1; s <= CUM_MAXD; ++s)
     CUM_TRY(launch_combine_batch(bt->prec, s, bt->d_comb[s], bt->comb_items[s], bt->ncomb[s], bt->comb_grid[s],
                                  bt->stage_bytes[s], bt->stream));
@@ -737,14 +811,37 @@ int cum_batch_create(cum_batch** out, cum_ctx* const* ctxs, int m) {
     bt->groups.push_back(g);
   }
 
-  // combine tables per order: one entry per context (unused when d < s)
+  // fused combine: members whose lattices fit, items grouped by order d
+  {
+    std::vector<LatArgs> la((size_t)m);
+    for (int i = 0; i < m; ++i)
+      if (ctxs[i]->lat_lds > 0) la[(size_t)i] = lat_args(ctxs[i]);
+    if (bupload(bt, &bt->d_lat, la.data(), la.size()) != hipSuccess) return fail(CUM_ENOMEM);
+    for (int dd = 1; dd <= CUM_MAXD; ++dd) {
+      std::vector<int64_t> items;
+      size_t lds = 16;
+      for (int i : order) {
+        cum_ctx* c = ctxs[i];
+        if (c->lat_lds == 0 || c->d != dd) continue;
+        for (int64_t blk = 0; blk < c->T.ord[dd].nblocks; ++blk) items.push_back(((int64_t)i << 40) | blk);
+        lds = std::max(lds, c->lat_lds);
+      }
+      if (items.empty()) continue;
+      bt->nlat[dd] = (int)items.size();
+      bt->lat_grid[dd] = std::min(bt->nlat[dd], ncu * 24);
+      bt->lat_lds[dd] = lds;
+      if (bupload(bt, &bt->lat_items[dd], items.data(), items.size()) != hipSuccess) return fail(CUM_ENOMEM);
+    }
+  }
+  // per-order combine of the other members: one entry per context (unused
+  // when d < s or the member uses the fused combine)
   for (int s = 1; s <= CUM_MAXD; ++s) {
     std::vector<CombArgs> args((size_t)m);
     std::vector<int64_t> items;
     size_t stage = 0;
     for (int i : order) {
       cum_ctx* c = ctxs[i];
-      if (c->d < s) continue;
+      if (c->d < s || c->lat_lds > 0) continue;
       CombArgs& a = args[(size_t)i];
       a.b = c->b;
       a.nbar = c->T.nbar;

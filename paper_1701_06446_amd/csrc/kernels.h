@@ -51,6 +51,32 @@ struct CombArgs {
   double* partial;          // per-block mult * sum(c^2)
 };
 
+// Fused combine of every order (one workgroup per order-d block): the
+// block's lattice of proper sub-blocks (one per non-empty proper subset of
+// its d index positions) is staged in LDS as moments, their cumulants are
+// formed level by level, then the block's own order-d cumulants; each
+// lower-order block is written by the one order-d block that extends its
+// tuple by repeating the last index (desig bit s: write the prefix-s block).
+constexpr size_t LAT_LDS_BYTES = 65536;
+
+struct LatArgs {
+  int b, log2b;
+  const int32_t* subrank;          // order d: per block and subset mask
+  const uint8_t* desig;            // order d: bit s set when the block writes its prefix-s block
+  double inv_t;
+  const void* s_hi[CUM_MAXD + 1];  // running sums (pair) per order
+  const void* s_lo[CUM_MAXD + 1];
+  double* C[CUM_MAXD + 1];         // cumulants per order (outputs)
+  const double* mult[CUM_MAXD + 1];
+  double* partial[CUM_MAXD + 1];   // per-block mult * sum(c^2)
+  int off[(1 << CUM_MAXD) + 1];    // LDS element offset of each proper sub-mask's sub-block; off[full] = total
+  int rec;                         // batched form: 1 = recursion, 0 = partition sum
+};
+
+// LDS bytes the fused combine needs for (d, b): moments and cumulants of the
+// (b+1)^d - 1 - b^d elements of the proper sub-blocks.
+size_t lattice_lds_bytes(int d, int b);
+
 struct NormArgs {
   int d;
   int kfirst;               // orders below kfirst already hold their norm in out[] (1: none)
@@ -67,6 +93,12 @@ int update_chunk_rows(int prec, int str);
 hipError_t launch_update(int prec, int tm, int tn, int kmax, const UpdArgs& a, int nitems, hipStream_t st);
 hipError_t launch_combine(int prec, int s, const CombArgs& a, int64_t nblocks, hipStream_t st);
 hipError_t launch_norms(const NormArgs& a, hipStream_t st);
+// recursion: c_I = m_I - sum over B containing I's first position of c_B m_{I\B}
+// (2^(s-1) - 1 terms) instead of the partition sum of Alg. 4 (B(s) - 1 terms)
+hipError_t launch_combine_lattice(int prec, int d, bool recursion, const LatArgs& a, int64_t nblocks,
+                                  size_t lds_bytes, hipStream_t st);
+hipError_t launch_combine_lattice_batch(int prec, int d, const LatArgs* ctxs, const int64_t* items, int nitems,
+                                        int grid, size_t lds_bytes, hipStream_t st);
 
 // Batched launches over several contexts (device-resident argument tables).
 hipError_t launch_update_batch(int prec, int str, bool vl, int kmax, const UpdArgs* ctxs, const UpdItem* items,

@@ -66,6 +66,14 @@ __device__ __forceinline__ void fold(T* hi_p, T* lo_p, T d) {
   *lo_p = nl;
 }
 
+// Sum over the 64 lanes of a wave by a fixed butterfly (every lane ends with
+// the same total, in the same order on every run).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
 // Chunks.  The rows of one contraction are the np rows of xp (sign +1) and
 // the nm rows of xm (sign -1).  They are cut into chunks of R rows that never
 // mix the two signs: ceil(np/R) plus chunks, then ceil(nm/R) minus chunks, the
@@ -609,7 +617,7 @@ __device__ void combine_block(const CombArgs& a, int64_t blk, double* stage) {
       int off = 0;
 #pragma unroll
       for (int q = 0; q < S; ++q)
-        if (mask & (1 << q)) off = off * b + dig[q];
+        if (mask & (1 << q)) off = (int)__umul24((unsigned)off, (unsigned)b) + dig[q];
       if constexpr (STAGE) {
         cB[mask] = stage[lds_off[mask] + off];
       } else {
@@ -623,13 +631,11 @@ __device__ void combine_block(const CombArgs& a, int64_t blk, double* stage) {
     a.Cout[o] = c;
     sq += c * c;
   }
-  red[tid] = sq;
+  // the same fixed order as the fused combine: wave butterfly, then waves 0..3
+  const double w = wave_sum(sq);
+  if ((tid & 63) == 0) red[tid >> 6] = w;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w) red[tid] += red[tid + w];
-    __syncthreads();
-  }
-  if (tid == 0) a.partial[blk] = a.mult[blk] * red[0];
+  if (tid == 0) a.partial[blk] = a.mult[blk] * (((red[0] + red[1]) + red[2]) + red[3]);
 }
 
 template <int S, typename St, bool STAGE>
@@ -651,36 +657,291 @@ __global__ __launch_bounds__(256) void k_combine_batch(const CombArgs* __restric
   }
 }
 
-// Final norms (Alg. 5 with exponent 2, Eq. (mef)): fro[k] = sqrt(sum of the
-// order's block partials), each order summed by a fixed thread/tree order;
-// nu[k] = fro[k] / fro[2]^(k/2) for k >= 3.  One workgroup of 1024 threads;
-// every thread issues its loads before summing, so an order costs about one
-// memory round trip.
-__device__ void norms_block(const NormArgs& a) {
-  __shared__ double red[1024];
-  __shared__ double fro[CUM_MAXD + 1];
-  const int tid = threadIdx.x;
-  if (tid < a.kfirst) fro[tid] = a.out[tid];  // written by the small-order kernel
-  for (int k = a.kfirst; k <= a.d; ++k) {
-    const double* p = a.partial[k];
-    const int64_t nb = a.nblocks[k];
-    double v[8];
+// ---------------------------------------------------------------------------
+// Fused combine over the sub-block lattice of one order-S block.
+
+__host__ __device__ constexpr int popc_c(int x) { return x ? (x & 1) + popc_c(x >> 1) : 0; }
+
+// Mask of the lattice positions picked by local mask q of the positions of m.
+__host__ __device__ constexpr int pdep_c(int q, int m) {
+  int r = 0, k = 0;
+  for (int p = 0; p < 8; ++p)
+    if (m & (1 << p)) {
+      if (q & (1 << k)) r |= 1 << p;
+      ++k;
+    }
+  return r;
+}
+
+// Sub-block element e of a mask with s positions -> its s digits (position
+// order, most significant first).
+template <int s>
+__device__ __forceinline__ void lat_digits(int e, int b, int lb, int (&dig)[s > 0 ? s : 1]) {
+  if (lb >= 0) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t i = tid + 1024 * u;
-      v[u] = i < nb ? p[i] : 0.0;
+    for (int q = s - 1; q >= 0; --q) dig[q] = (e >> (lb * (s - 1 - q))) & (b - 1);
+  } else {
+#pragma unroll
+    for (int q = s - 1; q >= 0; --q) {
+      dig[q] = e % b;
+      e /= b;
     }
-    double s = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
-    for (int64_t i = tid + 8192; i < nb; i += 1024) s += p[i];
-    red[tid] = s;
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
+  }
+}
+
+// The subtracted sum for element `dig` of the sub-block of MASK (s positions):
+// Alg. 4's sum over partitions into 2..s parts of products of cumulants, or
+// the recursion sum over B containing the first position of c_B * m_{MASK\B}.
+// Lattice LDS: moments at off[G], cumulants at tot + off[G] (singletons: the
+// moment is the cumulant).
+template <int s, int MASK, bool REC>
+__device__ __forceinline__ double lat_terms(const LatArgs& a, const double* lat, int tot, const int (&dig)[s > 0 ? s : 1],
+                                            int b) {
+  constexpr int NQ = 1 << s;
+  auto sub = [&](int q) __attribute__((always_inline)) {
+    int o = 0;
+#pragma unroll
+    for (int r = 0; r < s; ++r)
+      if (q & (1 << r)) o = (int)__umul24((unsigned)o, (unsigned)b) + dig[r];
+    return o;
+  };
+  if constexpr (REC) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 1; q < NQ - 1; q += 2) {
+      const int rest = (NQ - 1) & ~q;
+      const int G = pdep_c(q, MASK), H = pdep_c(rest, MASK);
+      const double cq = popc_c(q) == 1 ? lat[a.off[G] + sub(q)] : lat[tot + a.off[G] + sub(q)];
+      acc += cq * lat[a.off[H] + sub(rest)];
     }
-    if (tid == 0) fro[k] = sqrt(red[0]);
+    return acc;
+  } else {
+    double cB[NQ];
+#pragma unroll
+    for (int q = 1; q < NQ - 1; ++q) {
+      const int G = pdep_c(q, MASK);
+      cB[q] = popc_c(q) == 1 ? lat[a.off[G] + sub(q)] : lat[tot + a.off[G] + sub(q)];
+    }
+    cB[0] = 0.0;
+    cB[NQ - 1] = 0.0;
+    return partition_sum<s>(cB);
+  }
+}
+
+// Cumulants of the proper sub-block MASK from the staged lattice.
+template <int S, bool REC, int MASK>
+__device__ __forceinline__ void lat_mask(const LatArgs& a, double* lat, int tot) {
+  constexpr int s = popc_c(MASK);
+  const int b = a.b;
+  int size = 1;
+#pragma unroll
+  for (int q = 0; q < s; ++q) size *= b;
+  for (int e = threadIdx.x; e < size; e += 64) {
+    int dig[s];
+    lat_digits<s>(e, b, a.log2b, dig);
+    lat[tot + a.off[MASK] + e] = lat[a.off[MASK] + e] - lat_terms<s, MASK, REC>(a, lat, tot, dig, b);
+  }
+}
+
+template <int S, bool REC, int LEVEL, int MASK>
+__device__ __forceinline__ void lat_level(const LatArgs& a, double* lat, int tot) {
+  if constexpr (MASK < (1 << S) - 1) {
+    if constexpr (popc_c(MASK) == LEVEL) lat_mask<S, REC, MASK>(a, lat, tot);
+    lat_level<S, REC, LEVEL, MASK + 1>(a, lat, tot);
+  }
+}
+
+// One order-S block, one wave (64 lanes): stage the moments of the block's
+// proper sub-blocks, form their cumulants level by level, then the block's
+// own order-S cumulants, write the lower-order blocks this block is
+// designated for, and the weighted sums of squares of every block written.
+template <int S, typename St, bool REC>
+__device__ void lattice_block(const LatArgs& a, int64_t blk, double* lat) {
+  constexpr int NM = 1 << S;
+  constexpr int FULL = NM - 1;
+  constexpr int PRE = 4;  // own-block moments prefetched per lane
+  __shared__ int64_t sub_base[NM];
+  __shared__ const St* bhi[NM];
+  __shared__ const St* blo[NM];
+  const int tid = threadIdx.x;
+  const int b = a.b;
+  const int tot = a.off[FULL];
+  int bS = 1;
+#pragma unroll
+  for (int q = 0; q < S; ++q) bS *= b;
+
+  // the block's own running sums do not depend on the prologue
+  const St* shi = (const St*)a.s_hi[S];
+  const St* slo = (const St*)a.s_lo[S];
+  double mpre[PRE];
+#pragma unroll
+  for (int u = 0; u < PRE; ++u) {
+    const int e = tid + 64 * u;
+    const int64_t o = blk * bS + e;
+    mpre[u] = e < bS ? ((double)shi[o] + (double)slo[o]) * a.inv_t : 0.0;
+  }
+  const int des = a.desig[blk];
+  if (tid >= 1 && tid < FULL) {
+    const int ps = __builtin_popcount(tid);
+    int64_t bl = 1;
+    for (int q = 0; q < ps; ++q) bl *= b;
+    const int64_t sb = (int64_t)a.subrank[blk * NM + tid] * bl;
+    sub_base[tid] = sb;
+    const St* hi = nullptr;
+    const St* lo = nullptr;
+#pragma unroll
+    for (int k = 1; k < S; ++k)
+      if (ps == k) {
+        hi = (const St*)a.s_hi[k];
+        lo = (const St*)a.s_lo[k];
+      }
+    bhi[tid] = hi + sb;
+    blo[tid] = lo + sb;
+  }
+  __syncthreads();
+  // moments of every proper sub-block, four lattice elements per lane at a
+  // time with all their loads in flight together; element i belongs to the
+  // last mask whose offset is <= i
+  for (int i0 = 0; i0 < tot; i0 += 256) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + tid + 64 * u;
+      v[u] = 0.0;
+      if (i < tot) {
+        int m = 1, base = 0;
+#pragma unroll
+        for (int mm = 2; mm < FULL; ++mm)
+          if (i >= a.off[mm]) {
+            m = mm;
+            base = a.off[mm];
+          }
+        v[u] = ((double)bhi[m][i - base] + (double)blo[m][i - base]) * a.inv_t;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + tid + 64 * u;
+      if (i < tot) lat[i] = v[u];
+    }
+  }
+  __syncthreads();
+  // cumulants of the proper sub-blocks, one level (subset size) at a time
+  if constexpr (S >= 3) { lat_level<S, REC, 2, 1>(a, lat, tot); __syncthreads(); }
+  if constexpr (S >= 4) { lat_level<S, REC, 3, 1>(a, lat, tot); __syncthreads(); }
+  if constexpr (S >= 5) { lat_level<S, REC, 4, 1>(a, lat, tot); __syncthreads(); }
+  if constexpr (S >= 6) { lat_level<S, REC, 5, 1>(a, lat, tot); __syncthreads(); }
+
+  double sq[S + 1];
+#pragma unroll
+  for (int k = 0; k <= S; ++k) sq[k] = 0.0;
+  // the block's own order-S cumulants
+  double* Cout = a.C[S];
+  for (int e0 = 0; e0 < bS; e0 += 64 * PRE) {
+#pragma unroll
+    for (int u = 0; u < PRE; ++u) {
+      const int e = e0 + tid + 64 * u;
+      if (e < bS) {
+        int dig[S];
+        lat_digits<S>(e, b, a.log2b, dig);
+        const int64_t o = blk * bS + e;
+        const double m = e0 == 0 ? mpre[u] : ((double)shi[o] + (double)slo[o]) * a.inv_t;
+        const double c = m - lat_terms<S, FULL, REC>(a, lat, tot, dig, b);
+        Cout[o] = c;
+        sq[S] += c * c;
+      }
+    }
+  }
+  // the lower-order blocks this block is designated to write
+#pragma unroll
+  for (int s = 1; s < S; ++s) {
+    if (des & (1 << s)) {
+      const int mask = (1 << s) - 1;
+      const int size = a.off[mask + 1] - a.off[mask];
+      const int base = (s == 1 ? 0 : tot) + a.off[mask];
+      for (int e = tid; e < size; e += 64) {
+        const double c = lat[base + e];
+        a.C[s][sub_base[mask] + e] = c;
+        sq[s] += c * c;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 1; k <= S; ++k) {
+    if (k == S || (des & (1 << k))) {
+      const double t = wave_sum(sq[k]);
+      if (tid == 0) {
+        const int64_t kb = (k == S) ? blk : (int64_t)a.subrank[blk * NM + ((1 << k) - 1)];
+        a.partial[k][kb] = a.mult[k][kb] * t;
+      }
+    }
+  }
+}
+
+template <int S, typename St, bool REC>
+__global__ __launch_bounds__(64) void k_combine_lattice(LatArgs a) {
+  extern __shared__ __attribute__((aligned(16))) double lat[];
+  lattice_block<S, St, REC>(a, blockIdx.x, lat);
+}
+
+// Batched form: items[i] = (context << 40) | order-S block; contexts of one
+// order S whose lattices fit, each with its own formula flag.
+template <int S, typename St>
+__global__ __launch_bounds__(64) void k_combine_lattice_batch(const LatArgs* __restrict__ ctxs,
+                                                              const int64_t* __restrict__ items, int nitems) {
+  extern __shared__ __attribute__((aligned(16))) double lat[];
+  for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+    const int64_t w = items[i];
+    const LatArgs& a = ctxs[w >> 40];
+    const int64_t blk = w & ((int64_t(1) << 40) - 1);
+    if (a.rec) lattice_block<S, St, true>(a, blk, lat);
+    else lattice_block<S, St, false>(a, blk, lat);
     __syncthreads();
   }
+}
+
+// Final norms (Alg. 5 with exponent 2, Eq. (mef)): fro[k] = sqrt(sum of the
+// order's block partials); nu[k] = fro[k] / fro[2]^(k/2) for k >= 3.  One
+// workgroup of 1024 threads issues the loads of every order first, then
+// reduces all orders together in a fixed order (thread, wave butterfly, then
+// the 16 waves in index order): about one memory round trip.
+__device__ void norms_block(const NormArgs& a) {
+  __shared__ double red[CUM_MAXD + 1][16];
+  __shared__ double fro[CUM_MAXD + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double s[CUM_MAXD + 1];
+#pragma unroll
+  for (int k = 1; k <= CUM_MAXD; ++k) {
+    s[k] = 0.0;
+    if (k >= a.kfirst && k <= a.d) {
+      const double* p = a.partial[k];
+      const int64_t nb = a.nblocks[k];
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t i = tid + 1024 * u;
+        v[u] = i < nb ? p[i] : 0.0;
+      }
+      s[k] = (v[0] + v[1]) + (v[2] + v[3]);
+      for (int64_t i = tid + 4096; i < nb; i += 1024) s[k] += p[i];
+    }
+  }
+#pragma unroll
+  for (int k = 1; k <= CUM_MAXD; ++k) {
+    const double w = wave_sum(s[k]);
+    if (lane == 0) red[k][wv] = w;
+  }
+  __syncthreads();
+  if (tid >= 1 && tid <= a.d) {
+    if (tid < a.kfirst) {
+      fro[tid] = a.out[tid];  // written by the small-order kernel
+    } else {
+      double t = 0.0;
+      for (int w = 0; w < 16; ++w) t += red[tid][w];
+      fro[tid] = sqrt(t);
+    }
+  }
+  __syncthreads();
   if (tid <= a.d) {
     a.out[tid] = tid == 0 ? __builtin_nan("") : fro[tid];
     a.out[a.d + 1 + tid] = (tid >= 3) ? fro[tid] / pow(fro[2], 0.5 * tid) : __builtin_nan("");
@@ -884,6 +1145,64 @@ hipError_t launch_norms_batch(const NormArgs* ctxs, int m, hipStream_t st) {
   if (m <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_norms_batch, dim3(m), dim3(1024), 0, st, ctxs);
   return hipGetLastError();
+}
+
+template <int S, typename St>
+static hipError_t launch_lattice_s(bool rec, const LatArgs& a, int64_t nblocks, size_t lds, hipStream_t st) {
+  if (rec) hipLaunchKernelGGL((k_combine_lattice<S, St, true>), dim3((unsigned)nblocks), dim3(64), lds, st, a);
+  else hipLaunchKernelGGL((k_combine_lattice<S, St, false>), dim3((unsigned)nblocks), dim3(64), lds, st, a);
+  return hipGetLastError();
+}
+
+template <typename St>
+static hipError_t launch_lattice_t(int d, bool rec, const LatArgs& a, int64_t nblocks, size_t lds, hipStream_t st) {
+  switch (d) {
+    case 1: return launch_lattice_s<1, St>(rec, a, nblocks, lds, st);
+    case 2: return launch_lattice_s<2, St>(rec, a, nblocks, lds, st);
+    case 3: return launch_lattice_s<3, St>(rec, a, nblocks, lds, st);
+    case 4: return launch_lattice_s<4, St>(rec, a, nblocks, lds, st);
+    case 5: return launch_lattice_s<5, St>(rec, a, nblocks, lds, st);
+    case 6: return launch_lattice_s<6, St>(rec, a, nblocks, lds, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename St>
+static hipError_t launch_lattice_batch_t(int d, const LatArgs* ctxs, const int64_t* items, int nitems, int grid,
+                                         size_t lds, hipStream_t st) {
+  const dim3 g((unsigned)grid), blk(64);
+  switch (d) {
+    case 1: hipLaunchKernelGGL((k_combine_lattice_batch<1, St>), g, blk, lds, st, ctxs, items, nitems); break;
+    case 2: hipLaunchKernelGGL((k_combine_lattice_batch<2, St>), g, blk, lds, st, ctxs, items, nitems); break;
+    case 3: hipLaunchKernelGGL((k_combine_lattice_batch<3, St>), g, blk, lds, st, ctxs, items, nitems); break;
+    case 4: hipLaunchKernelGGL((k_combine_lattice_batch<4, St>), g, blk, lds, st, ctxs, items, nitems); break;
+    case 5: hipLaunchKernelGGL((k_combine_lattice_batch<5, St>), g, blk, lds, st, ctxs, items, nitems); break;
+    case 6: hipLaunchKernelGGL((k_combine_lattice_batch<6, St>), g, blk, lds, st, ctxs, items, nitems); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_combine_lattice_batch(int prec, int d, const LatArgs* ctxs, const int64_t* items, int nitems,
+                                        int grid, size_t lds_bytes, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  if (lds_bytes > LAT_LDS_BYTES) return hipErrorInvalidValue;
+  if (prec == PREC_F64) return launch_lattice_batch_t<double>(d, ctxs, items, nitems, grid, lds_bytes, st);
+  return launch_lattice_batch_t<float>(d, ctxs, items, nitems, grid, lds_bytes, st);
+}
+
+size_t lattice_lds_bytes(int d, int b) {
+  int64_t tot = 1, bd = 1;
+  for (int q = 0; q < d; ++q) { tot *= (b + 1); bd *= b; }
+  return (size_t)(tot - 1 - bd) * 2 * sizeof(double);
+}
+
+hipError_t launch_combine_lattice(int prec, int d, bool recursion, const LatArgs& a, int64_t nblocks,
+                                  size_t lds_bytes, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  if (lds_bytes > LAT_LDS_BYTES) return hipErrorInvalidValue;
+  if (prec == PREC_F64) return launch_lattice_t<double>(d, recursion, a, nblocks, lds_bytes, st);
+  return launch_lattice_t<float>(d, recursion, a, nblocks, lds_bytes, st);
 }
 
 hipError_t launch_norms(const NormArgs& a, hipStream_t st) {
