@@ -59,6 +59,10 @@ struct cum_ctx {
   // optional per-kernel timing: (class, start, stop) per launch of the
   // classes in profile_mask; events are recycled through a pool
   void* zero = nullptr;  // UPD_ZERO_BYTES zeros: padding source of the update's direct loads
+  // four tiles per workgroup: the items padded to groups of four with empty
+  // tiles (M = N = 0)
+  bool quad = false;
+  UpdItem* qitems = nullptr;
   // FIFO mode (fifo_p > 0): fifo_q = t / fifo_p slots of batch increments
   // per order, slot fifo_head holding the oldest batch of the window
   int64_t fifo_p = 0;
@@ -246,6 +250,8 @@ int run_contraction(cum_ctx* c, const char* xp, int64_t np, const char* xm, int6
     a.np = (int)cp;
     a.nm = (int)cm;
     a.vec = ((c->n * c->x_size) % 16 == 0) && ((uintptr_t)a.xp % 16 == 0) && ((uintptr_t)a.xm % 16 == 0);
+    a.quad = c->quad && a.vec;
+    a.items = a.quad ? c->qitems : c->items;
     Timed tm(c, 0);
     CUM_TRY(launch_update(c->prec, c->tm, c->tn, c->d, a, c->nitems, c->stream));
   }
@@ -434,6 +440,15 @@ int init_ctx(cum_ctx** out, int n, int d, int b, const void* X, int64_t t, int64
       return fail(e);
   }
   if ((e = upload(c, &c->items, items, &used)) != hipSuccess) return fail(e);
+  c->quad = update_quad_supported(prec, n) && !items.empty();
+  if (c->quad) {
+    std::vector<UpdItem> q = items;
+    UpdItem empty = items[0];
+    empty.M = 0;
+    empty.N = 0;
+    while (q.size() % 4) q.push_back(empty);
+    if ((e = upload(c, &c->qitems, q, &used)) != hipSuccess) return fail(e);
+  }
   if ((e = dalloc(c, (void**)&c->norms, (size_t)2 * (d + 1) * 8, &used)) != hipSuccess) return fail(e);
   if ((e = dalloc(c, &c->zero, UPD_ZERO_BYTES, &used)) != hipSuccess) return fail(e);
   if (lattice_lds_bytes(d, b) <= LAT_LDS_BYTES) {

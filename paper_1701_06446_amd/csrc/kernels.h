@@ -22,6 +22,7 @@ struct UpdArgs {
   int np, nm;
   int n;                    // data columns (LDS rows hold exactly n values)
   int vec;                  // 1: rows and both bases allow 16-byte copies
+  int quad;                 // 1: four tiles per workgroup (items padded to groups of four)
   const UpdItem* items;
   const void* zero;         // UPD_ZERO_BYTES of zeros (direct-path padding source)
   const LeftCol* left[CUM_MAXD + 1];
@@ -86,6 +87,7 @@ struct NormArgs {
 };
 
 bool update_tile_supported(int tm, int tn);
+bool update_quad_supported(int prec, int n);
 // LDS row stride (elements) used for n columns, 0 if n is too large.
 int update_lds_stride(int n);
 // Rows per LDS chunk for a precision and stride (0: not supported).

@@ -54,16 +54,22 @@ __device__ __forceinline__ f32x4 mma16(bf16x8 a, bf16x8 b, f32x4 c) {
 
 // Compensated fold of d into the pair (hi, lo): TwoSum then renormalise.
 template <typename T>
-__device__ __forceinline__ void fold(T* hi_p, T* lo_p, T d) {
-  const T hi = *hi_p, lo = *lo_p;
+__device__ __forceinline__ void fold_val(T& hi, T& lo, T d) {
   const T s = hi + d;
   const T bp = s - hi;
   const T err = (hi - (s - bp)) + (d - bp);
   const T l2 = lo + err;
   const T nh = s + l2;
-  const T nl = l2 - (nh - s);
-  *hi_p = nh;
-  *lo_p = nl;
+  lo = l2 - (nh - s);
+  hi = nh;
+}
+
+template <typename T>
+__device__ __forceinline__ void fold(T* hi_p, T* lo_p, T d) {
+  T hi = *hi_p, lo = *lo_p;
+  fold_val(hi, lo, d);
+  *hi_p = hi;
+  *lo_p = lo;
 }
 
 // Sum over the 64 lanes of a wave by a fixed butterfly (every lane ends with
@@ -267,6 +273,17 @@ __device__ void upd_body(const UpdArgs& a, const UpdItem& it, char* smem) {
   const int lgrp = (KS == 4 && NKS % 2 == 0) ? 2 * (lane >> 4) : (lane >> 4);
   const int lrow = DIRECT ? lgrp : wave * RW + lgrp;
   const int lbase = DIRECT ? wave * D::WU * 16 : 0;
+  const int ncp = (a.np + R - 1) / R;
+  const int nch = ncp + (a.nm + R - 1) / R;
+
+  // direct path: the copy of chunk 0 starts before anything else
+  DirectLanes<P, STR> dl;
+  char* wbuf = smem + (DIRECT ? wave * D::WU * 16 : 0);
+  if constexpr (DIRECT) {
+    direct_lanes<P, STR>(dl, a.n);
+    __syncthreads();  // the previous item's epilogue may still read smem
+    issue_chunk<P, STR>(wbuf, a, dl, 0, ncp, wave);
+  }
 
   // Byte addresses of this lane's factor columns at its first row.  Rows past
   // M, columns past N and padded data columns read column 0: their products
@@ -292,6 +309,31 @@ __device__ void upd_body(const UpdArgs& a, const UpdItem& it, char* smem) {
   int slot[PREF_UNITS];
   if constexpr (VL && !DIRECT) chunk_slots<P, STR>(slot, a.n);
 
+  // Epilogue element e = tid + 256 j of the tile (fragment j, row
+  // (tid >> 4) & 15, column tid & 15): its stored offset, or -1 past the
+  // pivot GEMM or on a padded column.  On the f32 path it is found here and
+  // the element's running sums are loaded right after the main loop.
+  constexpr int NF = TM * TN;
+  constexpr bool EPF = (P == PREC_F32);
+  auto elem_offset = [&](int j) __attribute__((always_inline)) -> int64_t {
+    const int f = j / TN, g = j - (j / TN) * TN;
+    const int r = it.r0 + 16 * f + ((tid >> 4) & 15), c = it.c0 + 16 * g + (tid & 15);
+    if (r >= it.M || c >= it.N) return -1;
+    const LeftCol L = left[it.lrow0 + r];
+    const RightCol Rc = right[it.rcol0 + c];
+    bool pad = false;
+#pragma unroll
+    for (int q = 0; q < H; ++q) pad = pad || L.c[q] >= a.n;
+#pragma unroll
+    for (int q = 0; q < MR; ++q) pad = pad || Rc.c[q] >= a.n;
+    return pad ? -1 : L.base + Rc.base;
+  };
+  int64_t eoff[NF];
+  if constexpr (EPF) {
+#pragma unroll
+    for (int j = 0; j < NF; ++j) eoff[j] = elem_offset(j);
+  }
+
   Acc acc[TM][TN];
 #pragma unroll
   for (int f = 0; f < TM; ++f)
@@ -299,9 +341,6 @@ __device__ void upd_body(const UpdArgs& a, const UpdItem& it, char* smem) {
     for (int g = 0; g < TN; ++g)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[f][g][r] = A1(0);
-
-  const int ncp = (a.np + R - 1) / R;
-  const int nch = ncp + (a.nm + R - 1) / R;
 
   // k-steps of one chunk held at byte offset BO of smem (f32/f64 paths)
   auto multiply_chunk = [&](auto bo_c) __attribute__((always_inline)) {
@@ -358,11 +397,6 @@ __device__ void upd_body(const UpdArgs& a, const UpdItem& it, char* smem) {
     // Per wave: wait for this wave's copy of chunk ci (its own loads only),
     // start the copy of chunk ci+1 into the other buffer (whose reads of
     // chunk ci-1 have completed), then run the k-steps of chunk ci.
-    DirectLanes<P, STR> dl;
-    direct_lanes<P, STR>(dl, a.n);
-    char* wbuf = smem + wave * D::WU * 16;
-    __syncthreads();  // the previous item's epilogue may still read smem
-    issue_chunk<P, STR>(wbuf, a, dl, 0, ncp, wave);
     auto run_chunk = [&](int ci) __attribute__((always_inline)) {
       __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
       if (ci + 1 < nch) issue_chunk<P, STR>(wbuf + ((ci + 1) & 1) * D::BUFB, a, dl, ci + 1, ncp, wave);
@@ -461,7 +495,6 @@ __device__ void upd_body(const UpdArgs& a, const UpdItem& it, char* smem) {
 
   // Reduce the four waves' partial sums in a fixed order (wave 0 + 1 + 2 + 3),
   // GF fragments at a time through LDS, and fold every stored element.
-  constexpr int NF = TM * TN;
   constexpr int LDSB = DIRECT ? D::SMEM : R * STR * ES;
   constexpr int GMAX = LDSB / (4 * 256 * (int)sizeof(A1));
   constexpr int GF = NF < GMAX ? NF : GMAX;
@@ -469,6 +502,44 @@ __device__ void upd_body(const UpdArgs& a, const UpdItem& it, char* smem) {
   A1* red = (A1*)smem;
   A1* shi = (A1*)a.s_hi[K_ORD];
   A1* slo = (A1*)a.s_lo[K_ORD];
+  A1* snp = (A1*)a.snap[K_ORD];
+  if constexpr (EPF && GF == NF) {
+    // the running sums of this lane's elements load while the partial sums
+    // pass through LDS
+    A1 ph[NF], pl[NF], ps[NF];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+      ph[j] = pl[j] = ps[j] = A1(0);
+      if (eoff[j] >= 0) {
+        ph[j] = shi[eoff[j]];
+        pl[j] = slo[eoff[j]];
+        if (a.fifo == 2) ps[j] = snp[eoff[j]];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NF; ++q) {
+      const int f = q / TN, g = q % TN;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        red[(wave * NF + q) * 256 + frag_row<P>(lane, r) * 16 + (lane & 15)] = acc[f][g][r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+      if (eoff[j] >= 0) {
+        const int e = tid + 256 * j;
+        const A1 sum = ((red[e] + red[NF * 256 + e]) + red[2 * NF * 256 + e]) + red[3 * NF * 256 + e];
+        fold_val<A1>(ph[j], pl[j], sum);
+        // FIFO: the batch leaving the window, its increment exactly as it was added
+        if (a.fifo == 2) fold_val<A1>(ph[j], pl[j], -ps[j]);
+        shi[eoff[j]] = ph[j];
+        slo[eoff[j]] = pl[j];
+        if (a.fifo) snp[eoff[j]] = sum;
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int f0 = 0; f0 < NF; f0 += GF) {
     __syncthreads();
@@ -976,6 +1047,285 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_B
   }
 }
 
+// ---------------------------------------------------------------------------
+// Four tiles per workgroup (f32/f64 rows of 16-byte multiples): 16 waves,
+// wave w works on tile w / 4 with row group w % 4 of every chunk.  A row
+// group's rows are copied into LDS once (the four waves that use them split
+// the copy) and read by all four tiles, so each chunk row crosses a CU's
+// load path once per four tiles.  One workgroup-wide barrier per chunk: after
+// it the chunk is in its buffer for everyone and nobody reads the other
+// buffer any more, so the copy of the next chunk starts before the k-steps.
+
+template <int P, int STR> struct QuadGeom {
+  static constexpr int ES = (P == PREC_F64) ? 8 : 4;
+  static constexpr int X = UPD_DIRECT_BYTES / (STR * ES);
+  static constexpr int RG = X >= 32 ? X / 32 * 32 : 16;      // rows per row group and chunk
+  static constexpr int R = 4 * RG;                          // rows per chunk
+  static constexpr int SU = STR * ES / 16;                  // 16-byte units per LDS row
+  static constexpr int GU = (RG * SU + 63) / 64 * 64;       // units per row-group buffer
+  static constexpr int NQ = GU / 64;                        // 64-lane copies per row group
+  static constexpr int BUFB = GU * 16;                      // one row group's chunk buffer, bytes
+  // row group g's two buffers sit at 2 g BUFB and (2 g + 1) BUFB, so every
+  // LDS read offset from a lane's base stays an immediate (< 64 KB)
+  static constexpr int REDB = 16 * 4 * 256 * ES;            // cross-wave reduction, bytes
+  static constexpr int SMEM = 8 * BUFB > REDB ? 8 * BUFB : REDB;
+  static constexpr bool OK = SMEM <= 163840;
+};
+
+template <int P, int STR> struct QuadLanes {
+  static constexpr int NQW = (QuadGeom<P, STR>::NQ + 3) / 4;  // copies per wave
+  uint32_t off[NQW];
+};
+
+// This lane's byte offsets (from its row group's first row) of the units it
+// copies: copy i of tile t is the row group's 64-unit slice t + 4 i.
+template <int P, int STR>
+__device__ __forceinline__ void quad_lanes(QuadLanes<P, STR>& ql, int n, int tile) {
+  using G = QuadGeom<P, STR>;
+  const int upr = n * G::ES / 16;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < QuadLanes<P, STR>::NQW; ++i) {
+    const int u = (tile + 4 * i) * 64 + lane;
+    const int r = u / G::SU, c = u - r * G::SU;
+    ql.off[i] = (c < upr && r < G::RG) ? (uint32_t)((r * upr + c) * 16) : 0u;
+  }
+}
+
+template <int P, int STR>
+__device__ __forceinline__ void quad_issue(char* gbuf, const UpdArgs& a, const QuadLanes<P, STR>& ql, int ci,
+                                           int ncp, int rg, int tile) {
+  using G = QuadGeom<P, STR>;
+  const int upr = a.n * G::ES / 16;
+  const bool plus = ci < ncp;
+  const int r0 = (plus ? ci : ci - ncp) * G::R + rg * G::RG;
+  const int rows = (plus ? a.np : a.nm) - r0;
+  const char* src = (const char*)(plus ? a.xp : a.xm) + (int64_t)r0 * upr * 16;
+  const uint32_t lim = rows >= G::RG ? 0xffffffffu : (rows > 0 ? (uint32_t)(rows * upr * 16) : 0u);
+#pragma unroll
+  for (int i = 0; i < QuadLanes<P, STR>::NQW; ++i) {
+    const int q = tile + 4 * i;
+    if (q < G::NQ) {
+      const char* g = ql.off[i] < lim ? src + ql.off[i] : (const char*)a.zero;
+      __builtin_amdgcn_global_load_lds((const void*)g,
+                                       (__attribute__((address_space(3))) void*)(gbuf + q * 1024), 16, 0, 0);
+    }
+  }
+}
+
+template <int P, int H, int MR, int STR>
+__device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
+  constexpr int TM = 2, TN = 2, NF = 4;
+  using T = typename Tr<P>::X;
+  using Acc = typename Tr<P>::Acc;
+  using A1 = typename Tr<P>::A1;
+  using G = QuadGeom<P, STR>;
+  constexpr int ES = G::ES;
+  constexpr int NKS = G::RG / 4;
+  constexpr int K_ORD = H + MR;
+  constexpr int MRC = MR > 0 ? MR : 1;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int tile = wave >> 2, rg = wave & 3;
+  const int ltid = tid & 255;  // thread index inside the tile's four waves
+  const LeftCol* __restrict__ left = a.left[K_ORD];
+  const RightCol* __restrict__ right = a.right[K_ORD];
+  const int R = G::R;
+  const int ncp = (a.np + R - 1) / R;
+  const int nch = ncp + (a.nm + R - 1) / R;
+
+  QuadLanes<P, STR> ql;
+  quad_lanes<P, STR>(ql, a.n, tile);
+  char* gbuf = smem + 2 * rg * G::BUFB;
+  quad_issue<P, STR>(gbuf, a, ql, 0, ncp, rg, tile);
+
+  const int lrow = (NKS % 2 == 0) ? 2 * (lane >> 4) : (lane >> 4);
+  const int lbase = 2 * rg * G::BUFB;
+  // empty tiles (the launch's padding) have M = N = 0 and read row/column 0
+  int ao[TM][H];
+  int bo[TN][MRC];
+#pragma unroll
+  for (int f = 0; f < TM; ++f) {
+    const int r = max(0, min(it.r0 + 16 * f + (lane & 15), it.M - 1));
+    const LeftCol L = left[it.lrow0 + r];
+#pragma unroll
+    for (int q = 0; q < H; ++q) ao[f][q] = lbase + (lrow * STR + (L.c[q] < a.n ? L.c[q] : 0)) * ES;
+  }
+#pragma unroll
+  for (int g = 0; g < TN; ++g) {
+    const int c = max(0, min(it.c0 + 16 * g + (lane & 15), it.N - 1));
+    const RightCol Rc = right[it.rcol0 + c];
+#pragma unroll
+    for (int q = 0; q < MRC; ++q) bo[g][q] = lbase + (lrow * STR + ((q < MR && Rc.c[q] < a.n) ? Rc.c[q] : 0)) * ES;
+  }
+  constexpr bool EPF = (P == PREC_F32);
+  auto elem_offset = [&](int j) __attribute__((always_inline)) -> int64_t {
+    const int f = j / TN, g = j - (j / TN) * TN;
+    const int r = it.r0 + 16 * f + ((ltid >> 4) & 15), c = it.c0 + 16 * g + (ltid & 15);
+    if (r >= it.M || c >= it.N) return -1;
+    const LeftCol L = left[it.lrow0 + r];
+    const RightCol Rc = right[it.rcol0 + c];
+    bool pad = false;
+#pragma unroll
+    for (int q = 0; q < H; ++q) pad = pad || L.c[q] >= a.n;
+#pragma unroll
+    for (int q = 0; q < MR; ++q) pad = pad || Rc.c[q] >= a.n;
+    return pad ? -1 : L.base + Rc.base;
+  };
+  int64_t eoff[NF];
+  if constexpr (EPF) {
+#pragma unroll
+    for (int j = 0; j < NF; ++j) eoff[j] = elem_offset(j);
+  }
+
+  Acc acc[TM][TN];
+#pragma unroll
+  for (int f = 0; f < TM; ++f)
+#pragma unroll
+    for (int g = 0; g < TN; ++g)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[f][g][r] = A1(0);
+
+  auto multiply_chunk = [&](auto bo_c) __attribute__((always_inline)) {
+    constexpr int BO = decltype(bo_c)::value;
+    constexpr bool PIPE = (P == PREC_F32);
+    constexpr int NB = PIPE ? 2 : 1;
+    T fa[NB][TM][H], fb[NB][TN][MRC];
+    auto load_factors = [&](int st, int buf) __attribute__((always_inline)) {
+      const int so = koff<NKS, STR, ES>(st) + BO;
+#pragma unroll
+      for (int f = 0; f < TM; ++f)
+#pragma unroll
+        for (int q = 0; q < H; ++q) fa[buf][f][q] = *(const T*)(smem + ao[f][q] + so);
+#pragma unroll
+      for (int g = 0; g < TN; ++g)
+#pragma unroll
+        for (int q = 0; q < MR; ++q) fb[buf][g][q] = *(const T*)(smem + bo[g][q] + so);
+    };
+    load_factors(0, 0);
+#pragma unroll
+    for (int st = 0; st < NKS; ++st) {
+      const int cur = PIPE ? (st & 1) : 0;
+      if (PIPE && st + 1 < NKS) load_factors(st + 1, cur ^ 1);
+      if (!PIPE && st > 0) load_factors(st, 0);
+      T A[TM], B[TN];
+#pragma unroll
+      for (int f = 0; f < TM; ++f) {
+        T v = fa[cur][f][0];
+#pragma unroll
+        for (int q = 1; q < H; ++q) v *= fa[cur][f][q];
+        A[f] = v;
+      }
+#pragma unroll
+      for (int g = 0; g < TN; ++g) {
+        T v = T(1);
+        if constexpr (MR > 0) {
+          v = fb[cur][g][0];
+#pragma unroll
+          for (int q = 1; q < MR; ++q) v *= fb[cur][g][q];
+        }
+        B[g] = v;
+      }
+#pragma unroll
+      for (int f = 0; f < TM; ++f)
+#pragma unroll
+        for (int g = 0; g < TN; ++g) acc[f][g] = mma(A[f], B[g], acc[f][g]);
+    }
+  };
+
+  auto run_chunk = [&](int ci) __attribute__((always_inline)) {
+    __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (ci + 1 < nch) quad_issue<P, STR>(gbuf + ((ci + 1) & 1) * G::BUFB, a, ql, ci + 1, ncp, rg, tile);
+    if (ci & 1) multiply_chunk(IntC<G::BUFB>{});
+    else multiply_chunk(IntC<0>{});
+  };
+  // sign: plus chunks, then the minus chunks into the negated accumulators
+  int ci = 0;
+  for (; ci < ncp; ++ci) run_chunk(ci);
+  if (nch > ncp) {
+#pragma unroll
+    for (int f = 0; f < TM; ++f)
+#pragma unroll
+      for (int g = 0; g < TN; ++g) acc[f][g] = -acc[f][g];
+    for (; ci < nch; ++ci) run_chunk(ci);
+#pragma unroll
+    for (int f = 0; f < TM; ++f)
+#pragma unroll
+      for (int g = 0; g < TN; ++g) acc[f][g] = -acc[f][g];
+  }
+
+  // each tile's four row-group partials, summed in a fixed order (row group
+  // 0 + 1 + 2 + 3), then the compensated fold of every stored element
+  A1* red = (A1*)smem;
+  A1* shi = (A1*)a.s_hi[K_ORD];
+  A1* slo = (A1*)a.s_lo[K_ORD];
+  A1* snp = (A1*)a.snap[K_ORD];
+  A1 ph[NF], pl[NF], ps[NF];
+  if constexpr (EPF) {
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+      ph[j] = pl[j] = ps[j] = A1(0);
+      if (eoff[j] >= 0) {
+        ph[j] = shi[eoff[j]];
+        pl[j] = slo[eoff[j]];
+        if (a.fifo == 2) ps[j] = snp[eoff[j]];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NF; ++q) {
+    const int f = q / TN, g = q % TN;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      red[((tile * 4 + rg) * NF + q) * 256 + frag_row<P>(lane, r) * 16 + (lane & 15)] = acc[f][g][r];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < NF; ++j) {
+    int64_t off;
+    if constexpr (EPF) off = eoff[j];
+    else off = elem_offset(j);
+    if (off >= 0) {
+      const int e = j * 256 + ltid;
+      const A1* rt = red + tile * 4 * NF * 256;
+      const A1 sum = ((rt[e] + rt[NF * 256 + e]) + rt[2 * NF * 256 + e]) + rt[3 * NF * 256 + e];
+      A1 h, l, sn = A1(0);
+      if constexpr (EPF) {
+        h = ph[j];
+        l = pl[j];
+        sn = ps[j];
+      } else {
+        h = shi[off];
+        l = slo[off];
+        if (a.fifo == 2) sn = snp[off];
+      }
+      fold_val<A1>(h, l, sum);
+      // FIFO: the batch leaving the window, its increment exactly as it was added
+      if (a.fifo == 2) fold_val<A1>(h, l, -sn);
+      shi[off] = h;
+      slo[off] = l;
+      if (a.fifo) snp[off] = sum;
+    }
+  }
+}
+
+template <int P, int STR, int KMAX>
+__global__ __launch_bounds__(1024) void k_update_quad(UpdArgs a) {
+  __shared__ __attribute__((aligned(16))) char smem[QuadGeom<P, STR>::SMEM];
+  const UpdItem it = a.items[blockIdx.x * 4 + (threadIdx.x >> 8)];
+  switch (it.k) {
+    case 1: upd_quad_body<P, 1, 0, STR>(a, it, smem); break;
+    case 2: upd_quad_body<P, 1, 1, STR>(a, it, smem); break;
+    case 3: upd_quad_body<P, 2, 1, STR>(a, it, smem); break;
+    case 4: upd_quad_body<P, 2, 2, STR>(a, it, smem); break;
+    case 5: if constexpr (KMAX >= 5) upd_quad_body<P, 3, 2, STR>(a, it, smem); break;
+    case 6: if constexpr (KMAX >= 6) upd_quad_body<P, 3, 3, STR>(a, it, smem); break;
+    default: break;
+  }
+}
+
 template <int P, int STR, bool VL>
 static hipError_t launch_batch_one(int kmax, const UpdArgs* ctxs, const UpdItem* items, int nitems, int grid,
                                    hipStream_t st) {
@@ -1019,8 +1369,36 @@ hipError_t launch_update_batch(int prec, int str, bool vl, int kmax, const UpdAr
 
 template <int P, int STR, bool VL>
 static void launch_kmax(int kmax, const UpdArgs& a, int nitems, hipStream_t st) {
+  if constexpr (VL && P != PREC_BF16X3 && QuadGeom<P, STR>::OK) {
+    if (a.quad) {
+      // a.items holds nitems rounded up to whole groups of four
+      const dim3 grid((unsigned)((nitems + 3) / 4));
+      if (kmax <= 4) hipLaunchKernelGGL((k_update_quad<P, STR, 4>), grid, dim3(1024), 0, st, a);
+      else hipLaunchKernelGGL((k_update_quad<P, STR, 6>), grid, dim3(1024), 0, st, a);
+      return;
+    }
+  }
   if (kmax <= 4) hipLaunchKernelGGL((k_update<P, 2, 2, STR, VL, 4>), dim3(nitems), dim3(256), 0, st, a);
   else hipLaunchKernelGGL((k_update<P, 2, 2, STR, VL, 6>), dim3(nitems), dim3(256), 0, st, a);
+}
+
+// Whether launch_update takes the four-tiles-per-workgroup kernel for this
+// precision and row length (16-byte rows, and its buffers fit in LDS).
+bool update_quad_supported(int prec, int n) {
+  const int str = update_lds_stride(n);
+  auto ok = [&](auto p) {
+    constexpr int PP = decltype(p)::value;
+    switch (str) {
+      case 36: return QuadGeom<PP, 36>::OK;
+      case 68: return QuadGeom<PP, 68>::OK;
+      case 132: return QuadGeom<PP, 132>::OK;
+      case 260: return QuadGeom<PP, 260>::OK;
+      default: return false;
+    }
+  };
+  if (prec == PREC_F32) return ok(IntC<PREC_F32>{});
+  if (prec == PREC_F64) return ok(IntC<PREC_F64>{});
+  return false;
 }
 
 template <int P, int STR>

@@ -27,3 +27,18 @@ def to_device(a: np.ndarray):
     import torch
 
     return torch.from_numpy(a).to("cuda")
+
+
+# Same window, different kernels (a batched member against its own single
+# context): the contraction sums rows in another order.  Each side is within
+# TOL of the exact cumulants (relative Frobenius over the full tensor), so
+# they agree to 2 TOL in the same measure.
+
+
+def assert_same_to_rounding(a, b, prec, what="", n=None, bb=None, k=None):
+    a, b = np.asarray(a), np.asarray(b)
+    if k is None:  # plain vectors (norms)
+        err = float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
+    else:
+        err = rel_err(a, b, n, bb, k)
+    assert err <= 2 * TOL[prec], (what, err)
