@@ -1158,7 +1158,9 @@ __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
 #pragma unroll
     for (int q = 0; q < MRC; ++q) bo[g][q] = lbase + (lrow * STR + ((q < MR && Rc.c[q] < a.n) ? Rc.c[q] : 0)) * ES;
   }
-  constexpr bool EPF = (P == PREC_F32);
+  // (the element offsets are found after the main loop: held through it they
+  // would push the allocation past 128 registers into scratch)
+  constexpr bool EPF = false;
   auto elem_offset = [&](int j) __attribute__((always_inline)) -> int64_t {
     const int f = j / TN, g = j - (j / TN) * TN;
     const int r = it.r0 + 16 * f + ((ltid >> 4) & 15), c = it.c0 + 16 * g + (ltid & 15);
