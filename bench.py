@@ -154,6 +154,20 @@ def run_path(path, s, warmup, steps, check):
         "launches_per_step": {"update": prof["update"][0] / steps, "combine": prof["combine"][0] / 10,
                               "norms": prof["norms"][0] / 10},
     }
+    # the recalculation the update replaces (Eq. (upcmplx), Sec. 3.3): the whole
+    # current window contracted from scratch on the same context, with the
+    # combine and norms; the paper's speed-up estimate is t / (2 t_up + B(d))
+    win = dev[w * P: w * P + T]
+    cum.cum_recompute(ctx, win)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(5):
+        cum.cum_recompute(ctx, win)
+    torch.cuda.synchronize()
+    rec_ms = (time.perf_counter() - t2) / 5 * 1e3
+    out["recompute_ms"] = rec_ms
+    out["speedup_vs_recompute"] = rec_ms / out["ms_per_step_without_kernel_events"]
+    out["speedup_theory"] = T / ((1 if mode == "fifo" else 2) * P + 15)  # B(4) = 15
     if check:
         window = rows[w * P: w * P + T].astype(np.float64)
         out["err_sampled"] = sampled_error(ctx, window, np.random.default_rng(7))

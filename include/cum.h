@@ -103,6 +103,18 @@ int cum_init(cum_ctx **ctx, int n, int d, int b, const void *X, int64_t t, int p
 int cum_update(cum_ctx *ctx, const void *X_new, const void *X_old, int64_t p);
 
 /*
+ * cum_recompute -- recalculate the context's moments from scratch over the
+ * window X (t x n rows, the t of cum_init, host or device, same element type
+ * as cum_init's), then its cumulants and norms: the recalculation that
+ * Eq. (upcmplx) and Sec. 3.3 compare the update with.  The running sums are
+ * zeroed first, so any rounding accumulated by earlier updates is dropped;
+ * a FIFO context (cum_init_fifo) refills its t/p batch slots from X's
+ * batches, oldest first.  Asynchronous on the context's stream for device X;
+ * host X is staged and the call synchronises.
+ */
+int cum_recompute(cum_ctx *ctx, const void *X);
+
+/*
  * cum_init_fifo -- like cum_init, but the context keeps the FIFO of batch
  * moments that Sec. 3.1 describes as the alternative to contracting the rows
  * that leave the window: the window is cut into t/p batches of p rows

@@ -34,7 +34,7 @@ EXPORTS = ("cum_init", "cum_update", "cum_get", "cum_get_moments", "cum_norms",
            "cum_strerror", "cum_last_error", "cum_plan_coverage", "cum_plan_items",
            "cum_profile_enable", "cum_profile_read", "cum_batch_create", "cum_batch_update",
            "cum_batch_sync", "cum_batch_free", "cum_loss_grad",
-           "cum_init_fifo", "cum_set_combine")
+           "cum_init_fifo", "cum_set_combine", "cum_recompute")
 
 
 class CumError(RuntimeError):
@@ -73,6 +73,7 @@ def _load():
         "cum_batch_sync": (i32, [vp]),
         "cum_batch_free": (i32, [vp]),
         "cum_set_combine": (i32, [vp, i32]),
+        "cum_recompute": (i32, [vp, vp]),
         "cum_init_fifo": (i32, [ctypes.POINTER(vp), i32, i32, i32, vp, i64, i64, i32, vp]),
         "cum_loss_grad": (i32, [i32, i32, i32, vp, i64, vp, ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_double), vp, vp, vp]),
@@ -154,6 +155,15 @@ def cum_init_fifo(n: int, d: int, b: int, X, p: int, prec="fp32", stream=None) -
     st = None if stream is None else ctypes.c_void_p(int(stream))
     _check(_lib.cum_init_fifo(ctypes.byref(h), n, d, b, addr, t, p, pr, st), "cum_init_fifo")
     return Context(h, n, d, b, t, pr, fifo_p=p)
+
+
+def cum_recompute(ctx: Context, X):
+    """Recalculate moments, cumulants and norms from scratch over the window X
+    (t x n, the context's t)."""
+    addr, t, _keep = _pointer(X, ctx.prec, ctx.n)
+    if t != ctx.t:
+        raise ValueError("cum_recompute needs the whole window: %d rows, got %d" % (ctx.t, t))
+    _check(_lib.cum_recompute(ctx.handle, addr), "cum_recompute")
 
 
 COMBINE = {"partitions": 0, "recursion": 1}

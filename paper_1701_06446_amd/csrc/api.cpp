@@ -571,6 +571,41 @@ int cum_update(cum_ctx* c, const void* X_new, const void* X_old, int64_t p) {
   return run_combine_and_norms(c);
 }
 
+int cum_recompute(cum_ctx* c, const void* X) {
+  if (!c || !X) return CUM_EINVAL;
+  if (!c->ready) return CUM_ESTATE;
+  const size_t wbytes = (size_t)c->t * c->n * c->x_size;
+  const char* xw = (const char*)X;
+  if (!is_device_ptr(X)) {
+    int rc = ensure_stage(c, wbytes);
+    if (rc != CUM_OK) return rc;
+    CUM_TRY(hipMemcpyAsync(c->stage, X, wbytes, hipMemcpyHostToDevice, c->stream));
+    xw = (const char*)c->stage;
+  }
+  if (c->batch_done) {
+    CUM_TRY(hipStreamWaitEvent(c->stream, c->batch_done, 0));
+    c->direct_since_batch = true;
+  }
+  for (int k = 1; k <= c->d; ++k) {
+    const size_t bytes = (size_t)c->T.ord[k].nelems * c->st_size;
+    CUM_TRY(hipMemsetAsync(c->s_hi[k], 0, bytes, c->stream));
+    CUM_TRY(hipMemsetAsync(c->s_lo[k], 0, bytes, c->stream));
+  }
+  int rc = CUM_OK;
+  if (c->fifo_q) {
+    const size_t bb = (size_t)c->fifo_p * c->n * c->x_size;
+    for (int q = 0; q < c->fifo_q && rc == CUM_OK; ++q)
+      rc = run_contraction(c, xw + (size_t)q * bb, c->fifo_p, nullptr, 0, 1, q);
+    c->fifo_head = 0;
+  } else {
+    rc = run_contraction(c, xw, c->t, nullptr, 0);
+  }
+  if (rc != CUM_OK) return rc;
+  rc = run_combine_and_norms(c);
+  if (rc == CUM_OK && xw != (const char*)X) CUM_TRY(hipStreamSynchronize(c->stream));
+  return rc;
+}
+
 int cum_get(cum_ctx* c, int k, double* blocks, size_t capacity_elems) {
   if (!c) return CUM_EINVAL;
   if (!c->ready) return CUM_ESTATE;
