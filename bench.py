@@ -97,7 +97,7 @@ def sampled_error(ctx, window: np.ndarray, rng, count: int = 40):
     return worst
 
 
-def run_path(path, s, warmup, steps, check):
+def run_path(path, s, warmup, steps, check, host_leg=False):
     """path: a precision (sliding mode: the new and the leaving rows are both
     contracted) or '<precision>-fifo' (the batch-increment queue)."""
     import torch
@@ -154,6 +154,16 @@ def run_path(path, s, warmup, steps, check):
         "launches_per_step": {"update": prof["update"][0] / steps, "combine": prof["combine"][0] / 10,
                               "norms": prof["norms"][0] / 10},
     }
+    if host_leg:
+        # the same updates from host (pageable numpy) rows: each call stages
+        # both batches over PCIe and waits for the copies (never `value`)
+        t3 = time.perf_counter()
+        for _ in range(20):
+            w += 1
+            lo, hi = (w - 1) * P, w * P
+            cum.cum_update(ctx, rows[T + lo:T + hi], None if mode == "fifo" else rows[lo:hi])
+        torch.cuda.synchronize()
+        out["host_input_rows_per_s"] = 20 * P / (time.perf_counter() - t3)
     # the recalculation the update replaces (Eq. (upcmplx), Sec. 3.3): the whole
     # current window contracted from scratch on the same context, with the
     # combine and norms; the paper's speed-up estimate is t / (2 t_up + B(d))
@@ -289,14 +299,14 @@ def main():
 
     import streams
 
-    total_steps = max(200, args.warmup + 2 * args.steps + 10)
+    total_steps = max(200, args.warmup + 2 * args.steps + 30)
     s = streams.regime_change_stream(n=N, d=D, b=B, t=T, p=P, steps=total_steps, switch=100)
     paths = [p for p in args.paths.split(",") if p and p != args.prec] + [args.prec]
     res = {}
     for prec in paths:
         print("[bench] path %s: warmup %d, %d timed steps" % (prec, args.warmup, args.steps),
               file=sys.stderr, flush=True)
-        res[prec] = run_path(prec, s, args.warmup, args.steps, not args.no_check)
+        res[prec] = run_path(prec, s, args.warmup, args.steps, not args.no_check, host_leg=(prec == args.prec))
         print("[bench] path %s: %.3f ms/step" % (prec, res[prec]["ms_per_step"]), file=sys.stderr, flush=True)
     for path, r in res.items():
         rows_contracted = P if path.endswith("-fifo") else 2 * P
