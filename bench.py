@@ -255,6 +255,81 @@ def run_batched(steps, warmup, prec="fp32", autotune=True):
             "autotune_s": tune_s, "err_sampled_max": worst, "tol": TOL[prec]}
 
 
+def run_order6(steps=4, warmup=1):
+    """The order-6 workload: mixed Exp(1) sources, n=48, d=6, b=4, t=50000,
+    p=2000, fp32 sliding mode; per-kernel times from the event profiler and
+    the sampled error against the per-element FP64 oracle."""
+    import torch
+
+    import paper_1701_06446_amd as cum
+    import streams
+    from oracle.element import cumulant_at, sample_elements
+
+    n, d, b, t, p = 48, 6, 4, 50000, 2000
+    s = streams.mixed_exp_stream(steps=warmup + steps)
+    rows = np.ascontiguousarray(s.rows.astype(np.float32))
+    dev = torch.from_numpy(rows).to("cuda")
+    t0 = time.perf_counter()
+    ctx = cum.cum_init(n, d, b, dev[:t])
+    init_s = time.perf_counter() - t0
+    w = 0
+
+    def step():
+        nonlocal w
+        w += 1
+        cum.cum_update(ctx, dev[t + (w - 1) * p:t + w * p], dev[(w - 1) * p:w * p])
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    cum.cum_profile_enable(ctx, True)
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    prof = cum.cum_profile_read(ctx)
+    cum.cum_profile_enable(ctx, False)
+    elems = [cum.cum_num_elems(n, b, k) for k in range(1, d + 1)]
+    flops = 2.0 * 2 * p * sum(elems)
+    upd_ms = prof["update"][1] / prof["update"][0]
+    window = rows[w * p:w * p + t].astype(np.float64)
+    rng = np.random.default_rng(17)
+    cache, worst = {}, 0.0
+    for k in range(2, d + 1):
+        offs, idxs = sample_elements(n, b, k, 12, rng)
+        ref = np.array([cumulant_at(window, idx, cache) for idx in idxs])
+        worst = max(worst, float(np.linalg.norm(cum.cum_get(ctx, k)[offs] - ref) / np.linalg.norm(ref)))
+    cum.cum_free(ctx)
+    return {"workload": "mixed Exp(1) sources S W, n=48 d=6 b=4 t=50000 p=2000, fp32 sliding",
+            "steps": steps, "ms_per_step": el / steps * 1e3, "rows_per_s": steps * p / el,
+            "kernel_ms": {k: v[1] / v[0] for k, v in prof.items() if v[0]},
+            "update_tflops": flops / (upd_ms * 1e-3) / 1e12, "update_frac_fp32_peak": flops / (upd_ms * 1e-3) / 1e12 / 157.3,
+            "flops_per_update": flops, "stored_elements": sum(elems), "init_s": init_s,
+            "err_sampled": worst, "tol": TOL["fp32"]}
+
+
+def run_adjoint(reps=5):
+    """The adjoint workload: L = ||C_3(X W^T)||^2 + ||C_4(X W^T)||^2 with
+    X 10000 x 32 and W 32 x 32 (d=4, b=4); loss and both gradients per call."""
+    import torch
+
+    import paper_1701_06446_amd as cum
+    import streams
+
+    X, W = streams.adjoint_workload()
+    Xd = torch.from_numpy(np.ascontiguousarray(X.astype(np.float32))).cuda()
+    Wd = torch.from_numpy(np.ascontiguousarray(W.astype(np.float32))).cuda()
+    L, _, _ = cum.cum_loss_grad(Xd, Wd, 4, 4, {3: 1.0, 4: 1.0})
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        cum.cum_loss_grad(Xd, Wd, 4, 4, {3: 1.0, 4: 1.0})
+    torch.cuda.synchronize()
+    return {"workload": "X 10000x32, W 32x32, d=4 b=4, weights {3: 1, 4: 1}", "loss": L,
+            "ms_per_call": (time.perf_counter() - t0) / reps * 1e3}
+
+
 def cpu_baseline(s, budget_s=12.0):
     """The oracle (as it stands) on the host cores: sliding steps of p=1000 rows
     at n=60, d=4, b=4 from a 2000-row start window, each step = compensated
@@ -289,6 +364,7 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-stream batched leg")
+    ap.add_argument("--no-extra", action="store_true", help="skip the order-6 and adjoint legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -342,6 +418,12 @@ def main():
     }
     if args.copy_calibration:
         line["copy_calibration"] = copy_calibration(args.copy_calibration)
+    if not args.no_extra:
+        print("[bench] order 6: n=48 d=6 b=4 p=2000", file=sys.stderr, flush=True)
+        line["order6"] = run_order6()
+        print("[bench] order 6: %.3f ms/step" % line["order6"]["ms_per_step"], file=sys.stderr, flush=True)
+        print("[bench] adjoint", file=sys.stderr, flush=True)
+        line["adjoint"] = run_adjoint()
     if not args.no_batched:
         print("[bench] batched: 64 streams, 40 steps", file=sys.stderr, flush=True)
         line["batched"] = run_batched(steps=40, warmup=3)
