@@ -258,6 +258,21 @@ int cum_loss_grad(int n, int d, int b, const float *X, int64_t t, const float *W
                   double *L, float *dX, float *dW, void *hip_stream);
 
 /*
+ * The same contrast and gradients for repeated calls at one shape (an
+ * optimisation loop over W): cum_loss_plan_create allocates, once, the
+ * context over Y = X W^T, the reverse-pass buffers and the per-column table
+ * of the derivative of Eq. (mom); cum_loss_plan_grad then runs one forward
+ * and reverse pass (arguments and results as for cum_loss_grad; synchronises
+ * the plan's stream); cum_loss_plan_free releases everything.  Limits and
+ * errors as for cum_loss_grad; a plan is not thread-safe.
+ */
+typedef struct cum_loss_plan cum_loss_plan;
+int cum_loss_plan_create(cum_loss_plan **plan, int n, int d, int b, int64_t t, void *hip_stream);
+int cum_loss_plan_grad(cum_loss_plan *plan, const float *X, const float *W, const double *w, double *L,
+                       float *dX, float *dW);
+int cum_loss_plan_free(cum_loss_plan *plan);
+
+/*
  * cum_plan_coverage -- host-only check of the update's pivot decomposition
  * (no GPU needed): for order k, counts how many (pivot, row, column)
  * products of the update land on each stored element (written to `hits`,

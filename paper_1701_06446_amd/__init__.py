@@ -34,7 +34,8 @@ EXPORTS = ("cum_init", "cum_update", "cum_get", "cum_get_moments", "cum_norms",
            "cum_strerror", "cum_last_error", "cum_plan_coverage", "cum_plan_items",
            "cum_profile_enable", "cum_profile_read", "cum_batch_create", "cum_batch_update",
            "cum_batch_sync", "cum_batch_free", "cum_loss_grad",
-           "cum_init_fifo", "cum_set_combine", "cum_recompute")
+           "cum_init_fifo", "cum_set_combine", "cum_recompute", "cum_loss_plan_create",
+           "cum_loss_plan_grad", "cum_loss_plan_free")
 
 
 class CumError(RuntimeError):
@@ -74,6 +75,10 @@ def _load():
         "cum_batch_free": (i32, [vp]),
         "cum_set_combine": (i32, [vp, i32]),
         "cum_recompute": (i32, [vp, vp]),
+        "cum_loss_plan_create": (i32, [ctypes.POINTER(vp), i32, i32, i32, i64, vp]),
+        "cum_loss_plan_grad": (i32, [vp, vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                     vp, vp]),
+        "cum_loss_plan_free": (i32, [vp]),
         "cum_init_fifo": (i32, [ctypes.POINTER(vp), i32, i32, i32, vp, i64, i64, i32, vp]),
         "cum_loss_grad": (i32, [i32, i32, i32, vp, i64, vp, ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_double), vp, vp, vp]),
@@ -327,9 +332,29 @@ def cum_batch_free(batch: Batch):
         batch.handle = None
 
 
+class LossPlan:
+    """Owns one ``cum_loss_plan`` (buffers and tables for one (n, d, b, t))."""
+
+    def __init__(self, n, d, b, t, stream=None):
+        self.n, self.d, self.b, self.t = n, d, b, t
+        h = ctypes.c_void_p()
+        st = None if stream is None else ctypes.c_void_p(int(stream))
+        _check(_lib.cum_loss_plan_create(ctypes.byref(h), n, d, b, t, st), "cum_loss_plan_create")
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.cum_loss_plan_free(self.handle)
+            self.handle = None
+
+
+_loss_plans = {}
+
+
 def cum_loss_grad(X, W, d=4, b=4, weights=None, stream=None):
     """L = sum_k weights[k] ||C_k(X W^T)||_F^2 and (dL/dX, dL/dW) from the HIP
-    adjoint.  X: (t, n), W: (n, n), contiguous float32 device tensors."""
+    adjoint.  X: (t, n), W: (n, n), contiguous float32 device tensors.  One
+    plan per (n, d, b, t, stream) is kept for the process."""
     import torch
 
     weights = weights or {3: 1.0, 4: 1.0}
@@ -341,8 +366,12 @@ def cum_loss_grad(X, W, d=4, b=4, weights=None, stream=None):
     w = (ctypes.c_double * (d + 1))(*[float(weights.get(k, 0.0)) for k in range(d + 1)])
     L = ctypes.c_double()
     st = torch.cuda.current_stream().cuda_stream if stream is None else stream
-    _check(_lib.cum_loss_grad(n, d, b, X.data_ptr(), t, W.data_ptr(), w, ctypes.byref(L), dX.data_ptr(),
-                              dW.data_ptr(), ctypes.c_void_p(st)), "cum_loss_grad")
+    key = (n, d, b, t, int(st or 0))
+    plan = _loss_plans.get(key)
+    if plan is None:
+        plan = _loss_plans[key] = LossPlan(n, d, b, t, st)
+    _check(_lib.cum_loss_plan_grad(plan.handle, X.data_ptr(), W.data_ptr(), w, ctypes.byref(L), dX.data_ptr(),
+                                   dW.data_ptr()), "cum_loss_plan_grad")
     return L.value, dX, dW
 
 

@@ -16,30 +16,30 @@ struct RevArgs {
   double* Cbar[CUM_MAXD + 1];       // gradients w.r.t. the stored cumulants
 };
 
-// One (stored element, column) pair of Y_bar: the element's order and
-// offset, how often the column occurs in it, and its other s-1 indices.
-struct YbarEntry {
-  int32_t off;
-  uint8_t s, cnt;
-  uint8_t oth[CUM_MAXD - 1];
-};
+// Y_bar by stored blocks: grid (row tiles of 64, block groups); group g
+// covers items[gptr[g] .. gptr[g+1]) of (order << 28 | block); partial sums
+// part[g][row][col], then summed over g in index order.
+constexpr int YB_MAXCOLS = 72;  // ceil(n/b)*b for n <= 64, b <= 8
 
-struct YbarArgs {
-  int n;
+struct YbarBlockArgs {
+  int n, b, ncols;                  // ncols = ceil(n/b)*b
   int64_t t;
-  double inv_t;
   const float* Y;
   const double* Mbar[CUM_MAXD + 1];
-  const int64_t* colptr;            // n+1 offsets into entries
-  const YbarEntry* entries;
-  double* Ybar;                     // t x n
+  const uint8_t* tuples[CUM_MAXD + 1];
+  const int32_t* items;
+  const int32_t* gptr;
+  double* part;                     // groups x t x n
 };
+
+hipError_t launch_ybar_blocks(const YbarBlockArgs& a, int groups, hipStream_t st);
+hipError_t launch_ybar_sum(const double* part, int groups, int64_t t, int n, double inv_t, double* Ybar,
+                           hipStream_t st);
 
 hipError_t launch_linear(const float* X, const float* W, float* Y, int64_t t, int n, hipStream_t st);
 hipError_t launch_cbar_init(const double* C, const double* mult, double* Cbar, int64_t nelems, int64_t bk,
                             double two_w, hipStream_t st);
 hipError_t launch_combine_rev(int s, const RevArgs& a, int64_t nblocks, size_t lds_bytes, hipStream_t st);
-hipError_t launch_ybar(const YbarArgs& a, hipStream_t st);
 hipError_t launch_dx_dw(const double* Ybar, const float* X, const float* W, float* dX, float* dW, int64_t t,
                         int n, hipStream_t st);
 

@@ -1012,65 +1012,72 @@ int cum_batch_free(cum_batch* bt) {
 
 namespace {
 
-// Per data column j, every stored element (order s, offset) containing j,
-// the number of its indices equal to j and its other s-1 indices.
-void build_ybar_entries(const Tables& T, std::vector<int64_t>& colptr, std::vector<YbarEntry>& entries) {
-  const int n = T.n, b = T.b;
-  std::vector<std::vector<YbarEntry>> per(n);
-  for (int s = 1; s <= T.d; ++s) {
-    const OrderInfo& o = T.ord[s];
-    for (int64_t r = 0; r < o.nblocks; ++r) {
-      for (int64_t e = 0; e < o.bk; ++e) {
-        int idx[CUM_MAXD];
-        int64_t rem = e;
-        bool pad = false;
-        for (int q = s - 1; q >= 0; --q) {
-          idx[q] = T.tuples[s][(size_t)r * s + q] * b + (int)(rem % b);
-          rem /= b;
-          pad = pad || idx[q] >= n;
-        }
-        if (pad) continue;
-        for (int q = 0; q < s; ++q) {
-          bool first = true;
-          for (int u = 0; u < q; ++u) first = first && idx[u] != idx[q];
-          if (!first) continue;
-          YbarEntry en{};
-          en.off = (int32_t)(r * o.bk + e);
-          en.s = (uint8_t)s;
-          int cnt = 0, k = 0;
-          bool skipped = false;
-          for (int u = 0; u < s; ++u) {
-            if (idx[u] == idx[q]) ++cnt;
-            if (idx[u] == idx[q] && !skipped) { skipped = true; continue; }
-            en.oth[k++] = (uint8_t)idx[u];
-          }
-          en.cnt = (uint8_t)cnt;
-          per[(size_t)idx[q]].push_back(en);
-        }
-      }
+// Y_bar work items: every stored block as (order << 28 | block), orders
+// ascending, cut into `groups` contiguous ranges of equal element count.
+void build_ybar_items(const Tables& T, int groups, std::vector<int32_t>& items, std::vector<int32_t>& gptr) {
+  items.clear();
+  std::vector<int64_t> wt;
+  int64_t total = 0;
+  for (int s = 1; s <= T.d; ++s)
+    for (int64_t r = 0; r < T.ord[s].nblocks; ++r) {
+      items.push_back((int32_t)(((int64_t)s << 28) | r));
+      wt.push_back(T.ord[s].bk);
+      total += T.ord[s].bk;
     }
+  gptr.assign((size_t)groups + 1, (int32_t)items.size());
+  gptr[0] = 0;
+  int64_t acc = 0;
+  int g = 1;
+  for (size_t i = 0; i < items.size() && g < groups; ++i) {
+    acc += wt[i];
+    while (g < groups && acc * groups >= total * g) gptr[(size_t)g++] = (int32_t)(i + 1);
   }
-  colptr.assign((size_t)n + 1, 0);
-  entries.clear();
-  for (int j = 0; j < n; ++j) {
-    colptr[(size_t)j] = (int64_t)entries.size();
-    entries.insert(entries.end(), per[(size_t)j].begin(), per[(size_t)j].end());
-  }
-  colptr[(size_t)n] = (int64_t)entries.size();
 }
 
 }  // namespace
 
 extern "C" {
 
-int cum_loss_grad(int n, int d, int b, const float* X, int64_t t, const float* W, const double* w, double* L,
-                  float* dX, float* dW, void* hip_stream) {
+struct cum_loss_plan {
+  int n = 0, d = 0, b = 0;
+  int64_t t = 0;
+  hipStream_t st = nullptr;
+  cum_ctx* c = nullptr;  // FP32 context over Y = X W^T
+  float* Y = nullptr;
+  double* Cbar[CUM_MAXD + 1] = {};
+  uint8_t* tuples[CUM_MAXD + 1] = {};
+  int32_t* items = nullptr;
+  int32_t* gptr = nullptr;
+  int groups = 1;
+  double* part = nullptr;
+  double* Ybar = nullptr;
+  std::vector<void*> owned;
+};
+
+int cum_loss_plan_free(cum_loss_plan* pl) {
+  if (!pl) return CUM_OK;
+  if (pl->st || pl->c) (void)hipStreamSynchronize(pl->st);
+  if (pl->c) cum_free(pl->c);
+  for (void* p : pl->owned) (void)hipFree(p);
+  delete pl;
+  return CUM_OK;
+}
+
+int cum_loss_plan_create(cum_loss_plan** out, int n, int d, int b, int64_t t, void* hip_stream) {
+  if (!out) return CUM_EINVAL;
+  *out = nullptr;
   int rc = check_shape(n, d, b);
   if (rc != CUM_OK) return rc;
-  if (!X || !W || !w || !L || !dX || !dW || t < 1 || t > ((int64_t)1 << 31)) return CUM_EINVAL;
+  if (t < 1 || t > ((int64_t)1 << 31)) return CUM_EINVAL;
   // Y_bar stages 256 rows of Y (256 n floats) in LDS; the host table of
   // (element, column) pairs holds up to d entries per stored element
   if (n > 64) return CUM_ESIZE;
+  // the reverse combine keeps staged cumulants and their gradients in LDS
+  for (int s = 2; s <= d; ++s) {
+    int64_t tot = 1, bs = 1;
+    for (int q = 0; q < s; ++q) { tot *= (b + 1); bs *= b; }
+    if ((tot - 1 - bs) * 2 * (int64_t)sizeof(double) > 65536) return CUM_ESIZE;
+  }
   {
     Tables probe;
     if (build_tables(n, b, d, probe) != 0) return CUM_EINVAL;
@@ -1078,48 +1085,76 @@ int cum_loss_grad(int n, int d, int b, const float* X, int64_t t, const float* W
     for (int k = 1; k <= d; ++k) tot += probe.ord[k].nelems;
     if (tot > ((int64_t)1 << 24)) return CUM_ESIZE;
   }
-  // the reverse combine keeps staged cumulants and their gradients in LDS
-  for (int s = 2; s <= d; ++s) {
-    int64_t tot = 1, bs = 1;
-    for (int q = 0; q < s; ++q) { tot *= (b + 1); bs *= b; }
-    if ((tot - 1 - bs) * 2 * (int64_t)sizeof(double) > 65536) return CUM_ESIZE;
-  }
-  if (!is_device_ptr(X) || !is_device_ptr(W) || !is_device_ptr(dX) || !is_device_ptr(dW)) return CUM_EINVAL;
-  hipStream_t st = (hipStream_t)hip_stream;
-  std::vector<void*> tmp;
-  cum_ctx* c = nullptr;
-  auto done = [&](int r) {
-    (void)hipStreamSynchronize(st);
-    for (void* p : tmp) (void)hipFree(p);
-    if (c) cum_free(c);
+  cum_loss_plan* pl = new (std::nothrow) cum_loss_plan();
+  if (!pl) return CUM_ENOMEM;
+  pl->n = n; pl->d = d; pl->b = b; pl->t = t;
+  pl->st = (hipStream_t)hip_stream;
+  auto fail = [&](int r) {
+    cum_loss_plan_free(pl);
     return r;
   };
   auto alloc = [&](void** p, size_t bytes) {
     hipError_t e = hipMalloc(p, bytes ? bytes : 16);
-    if (e == hipSuccess) tmp.push_back(*p);
+    if (e == hipSuccess) pl->owned.push_back(*p);
+    else *p = nullptr;
     return e;
   };
-  float* Y = nullptr;
-  hipError_t e = alloc((void**)&Y, (size_t)t * n * sizeof(float));
-  if (e != hipSuccess) return done(map_err(e));
-  if ((e = launch_linear(X, W, Y, t, n, st)) != hipSuccess) return done(map_err(e));
-  if ((e = hipStreamSynchronize(st)) != hipSuccess) return done(map_err(e));
-  rc = cum_init(&c, n, d, b, Y, t, CUM_FP32, hip_stream);
-  if (rc != CUM_OK) return done(rc);
+  hipError_t e;
+  if ((e = alloc((void**)&pl->Y, (size_t)t * n * sizeof(float))) != hipSuccess) return fail(map_err(e));
+  if ((e = hipMemsetAsync(pl->Y, 0, (size_t)t * n * sizeof(float), pl->st)) != hipSuccess) return fail(map_err(e));
+  if ((e = hipStreamSynchronize(pl->st)) != hipSuccess) return fail(map_err(e));
+  rc = cum_init(&pl->c, n, d, b, pl->Y, t, CUM_FP32, hip_stream);
+  if (rc != CUM_OK) return fail(rc);
+  for (int k = 1; k <= d; ++k)
+    if ((e = alloc((void**)&pl->Cbar[k], (size_t)pl->c->T.ord[k].nelems * sizeof(double))) != hipSuccess)
+      return fail(map_err(e));
+  // Y_bar: row tiles of 64 times block groups, enough workgroups to fill the
+  // device, partial sums capped at 256 MB
+  const int64_t tiles = (t + 63) / 64;
+  int groups = (int)std::max<int64_t>(1, std::min<int64_t>(64, (2048 + tiles - 1) / tiles));
+  while (groups > 1 && (int64_t)groups * t * n * 8 > ((int64_t)256 << 20)) --groups;
+  pl->groups = groups;
+  std::vector<int32_t> items, gptr;
+  build_ybar_items(pl->c->T, groups, items, gptr);
+  auto up = [&](void** dst, const void* src, size_t bytes) {
+    hipError_t r = alloc(dst, bytes);
+    if (r == hipSuccess && bytes) r = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    return r;
+  };
+  for (int k = 1; k <= d; ++k)
+    if ((e = up((void**)&pl->tuples[k], pl->c->T.tuples[k].data(), pl->c->T.tuples[k].size())) != hipSuccess)
+      return fail(map_err(e));
+  if ((e = up((void**)&pl->items, items.data(), items.size() * sizeof(int32_t))) != hipSuccess)
+    return fail(map_err(e));
+  if ((e = up((void**)&pl->gptr, gptr.data(), gptr.size() * sizeof(int32_t))) != hipSuccess)
+    return fail(map_err(e));
+  if ((e = alloc((void**)&pl->part, (size_t)groups * t * n * sizeof(double))) != hipSuccess) return fail(map_err(e));
+  if ((e = alloc((void**)&pl->Ybar, (size_t)t * n * sizeof(double))) != hipSuccess) return fail(map_err(e));
+  *out = pl;
+  return CUM_OK;
+}
+
+int cum_loss_plan_grad(cum_loss_plan* pl, const float* X, const float* W, const double* w, double* L, float* dX,
+                       float* dW) {
+  if (!pl || !X || !W || !w || !L || !dX || !dW) return CUM_EINVAL;
+  if (!is_device_ptr(X) || !is_device_ptr(W) || !is_device_ptr(dX) || !is_device_ptr(dW)) return CUM_EINVAL;
+  cum_ctx* c = pl->c;
+  const int n = pl->n, d = pl->d, b = pl->b;
+  const int64_t t = pl->t;
+  hipStream_t st = pl->st;
+  CUM_TRY(launch_linear(X, W, pl->Y, t, n, st));
+  int rc = cum_recompute(c, pl->Y);
+  if (rc != CUM_OK) return rc;
   std::vector<double> fro((size_t)d + 1), nu((size_t)d + 1);
   rc = cum_norms(c, fro.data(), nu.data());
-  if (rc != CUM_OK) return done(rc);
+  if (rc != CUM_OK) return rc;
   double loss = 0.0;
   for (int k = 1; k <= d; ++k)
     if (w[k] != 0.0) loss += w[k] * fro[(size_t)k] * fro[(size_t)k];
   *L = loss;
-
-  double* Cbar[CUM_MAXD + 1] = {};
   for (int k = 1; k <= d; ++k) {
     const OrderInfo& o = c->T.ord[k];
-    if ((e = alloc((void**)&Cbar[k], (size_t)o.nelems * sizeof(double))) != hipSuccess) return done(map_err(e));
-    if ((e = launch_cbar_init(c->C[k], c->mult[k], Cbar[k], o.nelems, o.bk, 2.0 * w[k], st)) != hipSuccess)
-      return done(map_err(e));
+    CUM_TRY(launch_cbar_init(c->C[k], c->mult[k], pl->Cbar[k], o.nelems, o.bk, 2.0 * w[k], st));
   }
   for (int s = d; s >= 2; --s) {
     RevArgs ra{};
@@ -1128,41 +1163,43 @@ int cum_loss_grad(int n, int d, int b, const float* X, int64_t t, const float* W
     ra.subrank = c->subrank[s];
     for (int k = 1; k <= d; ++k) {
       ra.C[k] = c->C[k];
-      ra.Cbar[k] = Cbar[k];
+      ra.Cbar[k] = pl->Cbar[k];
     }
     int64_t tot = 1, bs = 1;
     for (int q = 0; q < s; ++q) { tot *= (b + 1); bs *= b; }
     const size_t lds = (size_t)(tot - 1 - bs) * 2 * sizeof(double);
-    if ((e = launch_combine_rev(s, ra, c->T.ord[s].nblocks, lds, st)) != hipSuccess) return done(map_err(e));
+    CUM_TRY(launch_combine_rev(s, ra, c->T.ord[s].nblocks, lds, st));
   }
-  std::vector<int64_t> colptr;
-  std::vector<YbarEntry> entries;
-  build_ybar_entries(c->T, colptr, entries);
-  int64_t* d_colptr = nullptr;
-  YbarEntry* d_entries = nullptr;
-  if ((e = alloc((void**)&d_colptr, colptr.size() * sizeof(int64_t))) != hipSuccess) return done(map_err(e));
-  if ((e = alloc((void**)&d_entries, entries.size() * sizeof(YbarEntry))) != hipSuccess) return done(map_err(e));
-  if ((e = hipMemcpy(d_colptr, colptr.data(), colptr.size() * sizeof(int64_t), hipMemcpyHostToDevice)) != hipSuccess)
-    return done(map_err(e));
-  if (!entries.empty() &&
-      (e = hipMemcpy(d_entries, entries.data(), entries.size() * sizeof(YbarEntry), hipMemcpyHostToDevice)) !=
-          hipSuccess)
-    return done(map_err(e));
-  double* Ybar = nullptr;
-  if ((e = alloc((void**)&Ybar, (size_t)t * n * sizeof(double))) != hipSuccess) return done(map_err(e));
-  YbarArgs ya{};
+  YbarBlockArgs ya{};
   ya.n = n;
+  ya.b = b;
+  ya.ncols = c->T.nbar * b;
   ya.t = t;
-  ya.inv_t = 1.0 / (double)t;
-  ya.Y = Y;
-  for (int k = 1; k <= d; ++k) ya.Mbar[k] = Cbar[k];
-  ya.colptr = d_colptr;
-  ya.entries = d_entries;
-  ya.Ybar = Ybar;
-  if ((e = launch_ybar(ya, st)) != hipSuccess) return done(map_err(e));
-  if ((e = launch_dx_dw(Ybar, X, W, dX, dW, t, n, st)) != hipSuccess) return done(map_err(e));
-  if ((e = hipStreamSynchronize(st)) != hipSuccess) return done(map_err(e));
-  return done(CUM_OK);
+  ya.Y = pl->Y;
+  for (int k = 1; k <= d; ++k) {
+    ya.Mbar[k] = pl->Cbar[k];
+    ya.tuples[k] = pl->tuples[k];
+  }
+  ya.items = pl->items;
+  ya.gptr = pl->gptr;
+  ya.part = pl->part;
+  CUM_TRY(launch_ybar_blocks(ya, pl->groups, st));
+  CUM_TRY(launch_ybar_sum(pl->part, pl->groups, t, n, 1.0 / (double)t, pl->Ybar, st));
+  CUM_TRY(launch_dx_dw(pl->Ybar, X, W, dX, dW, t, n, st));
+  CUM_TRY(hipStreamSynchronize(st));
+  return CUM_OK;
+}
+
+int cum_loss_grad(int n, int d, int b, const float* X, int64_t t, const float* W, const double* w, double* L,
+                  float* dX, float* dW, void* hip_stream) {
+  if (!X || !W || !w || !L || !dX || !dW) return CUM_EINVAL;
+  if (!is_device_ptr(X) || !is_device_ptr(W) || !is_device_ptr(dX) || !is_device_ptr(dW)) return CUM_EINVAL;
+  cum_loss_plan* pl = nullptr;
+  int rc = cum_loss_plan_create(&pl, n, d, b, t, hip_stream);
+  if (rc != CUM_OK) return rc;
+  rc = cum_loss_plan_grad(pl, X, W, w, L, dX, dW);
+  cum_loss_plan_free(pl);
+  return rc;
 }
 
 }  // extern "C"
