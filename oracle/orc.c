@@ -300,12 +300,12 @@ double orc_block_norm(int n, int b, int k, const double *A) {
 }
 
 /* Eq. (mef): fro[k] = ||C_k|| (k = 1..d), nu[k] = fro[k] / fro[2]^(k/2) for
- * k >= 3; nu[0..2] are set to NaN.  fro[0] is unused (NaN). */
+ * k >= 3 (NaN when ||C_2|| = 0); nu[0..2] are set to NaN.  fro[0] is unused (NaN). */
 void orc_norms(int n, int b, int d, const double *const *C, double *fro, double *nu) {
   fro[0] = NAN;
   for (int k = 1; k <= d; ++k) fro[k] = orc_block_norm(n, b, k, C[k - 1]);
   for (int k = 0; k <= d; ++k) {
-    if (k < 3 || d < 2) nu[k] = NAN;
+    if (k < 3 || d < 2 || !(fro[2] > 0.0)) nu[k] = NAN;  /* no scale: ||C_2|| = 0 */
     else nu[k] = fro[k] / pow(fro[2], 0.5 * k);
   }
 }

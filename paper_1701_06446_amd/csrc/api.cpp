@@ -442,11 +442,7 @@ int init_ctx(cum_ctx** out, int n, int d, int b, const void* X, int64_t t, int64
   if ((e = upload(c, &c->items, items, &used)) != hipSuccess) return fail(e);
   c->quad = update_quad_supported(prec, n) && !items.empty();
   if (c->quad) {
-    std::vector<UpdItem> q = items;
-    UpdItem empty = items[0];
-    empty.M = 0;
-    empty.N = 0;
-    while (q.size() % 4) q.push_back(empty);
+    const std::vector<UpdItem> q = pack_quads(items);
     if ((e = upload(c, &c->qitems, q, &used)) != hipSuccess) return fail(e);
   }
   if ((e = dalloc(c, (void**)&c->norms, (size_t)2 * (d + 1) * 8, &used)) != hipSuccess) return fail(e);

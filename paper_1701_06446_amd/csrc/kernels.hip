@@ -949,6 +949,224 @@ __device__ void lattice_block(const LatArgs& a, int64_t blk, double* lat) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same combine with the block edge b fixed at compile time (2, 4 or 8):
+// digits are shifts and masks, every lattice offset is a constant (the LDS
+// reads take immediate offsets), the sub-block positions are scalar loads and
+// the moments of all sub-blocks are loaded before any is stored.
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(IntC<I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+template <int S, int B> struct LatFix {
+  static constexpr int NM = 1 << S;
+  static constexpr int FULL = NM - 1;
+  static constexpr int LB = B == 2 ? 1 : (B == 4 ? 2 : 3);
+  static constexpr int size(int m) {
+    int r = 1;
+    for (int q = 0; q < popc_c(m); ++q) r *= B;
+    return r;
+  }
+  static constexpr int off(int m) {  // lattice offset of proper mask m (off(FULL) = total)
+    int o = 0;
+    for (int k = 1; k < m; ++k) o += size(k);
+    return o;
+  }
+  static constexpr int TOT = off(FULL);
+  static constexpr int BS = size(FULL);
+  static constexpr int slots(int m) { return (size(m) + 63) / 64; }
+  static constexpr int NSLOT = [] {
+    int n = 0;
+    for (int m = 1; m < FULL; ++m) n += slots(m);
+    return n;
+  }();
+  static constexpr int slot_mask(int i) {
+    for (int m = 1; m < FULL; ++m) {
+      if (i < slots(m)) return m;
+      i -= slots(m);
+    }
+    return 0;
+  }
+  static constexpr int slot_index(int i) {
+    for (int m = 1; m < FULL; ++m) {
+      if (i < slots(m)) return i;
+      i -= slots(m);
+    }
+    return 0;
+  }
+};
+
+template <int s, int LB>
+__device__ __forceinline__ void fix_digits(int e, int (&dig)[s > 0 ? s : 1]) {
+#pragma unroll
+  for (int q = 0; q < s; ++q) dig[q] = (e >> (LB * (s - 1 - q))) & ((1 << LB) - 1);
+}
+
+// Offset inside the sub-block picked by local mask q of the digits.
+template <int q, int s, int LB>
+__device__ __forceinline__ int fix_sub(const int (&dig)[s > 0 ? s : 1]) {
+  int o = 0;
+#pragma unroll
+  for (int r = 0; r < s; ++r)
+    if (q & (1 << r)) o = (o << LB) | dig[r];
+  return o;
+}
+
+// lat_terms with every offset a constant (same terms, same order).
+template <int S, int B, int s, int MASK, bool REC>
+__device__ __forceinline__ double fix_terms(const double* lat, const int (&dig)[s > 0 ? s : 1]) {
+  using G = LatFix<S, B>;
+  constexpr int NQ = 1 << s;
+  if constexpr (REC) {
+    double acc = 0.0;
+    static_for<0, NQ / 2 - 1>([&](auto ic) __attribute__((always_inline)) {
+      constexpr int q = 2 * decltype(ic)::value + 1;
+      constexpr int rest = (NQ - 1) & ~q;
+      constexpr int OC = (popc_c(q) == 1 ? 0 : G::TOT) + G::off(pdep_c(q, MASK));
+      constexpr int OM = G::off(pdep_c(rest, MASK));
+      acc += lat[OC + fix_sub<q, s, G::LB>(dig)] * lat[OM + fix_sub<rest, s, G::LB>(dig)];
+    });
+    return acc;
+  } else {
+    double cB[NQ];
+    static_for<1, NQ - 1>([&](auto ic) __attribute__((always_inline)) {
+      constexpr int q = decltype(ic)::value;
+      constexpr int OC = (popc_c(q) == 1 ? 0 : G::TOT) + G::off(pdep_c(q, MASK));
+      cB[q] = lat[OC + fix_sub<q, s, G::LB>(dig)];
+    });
+    cB[0] = 0.0;
+    cB[NQ - 1] = 0.0;
+    return partition_sum<s>(cB);
+  }
+}
+
+// Cumulants of every proper sub-block of one level (subset size LEVEL).
+template <int S, int B, bool REC, int LEVEL>
+__device__ __forceinline__ void fix_level(double* lat) {
+  using G = LatFix<S, B>;
+  static_for<1, G::FULL>([&](auto mc) __attribute__((always_inline)) {
+    constexpr int M = decltype(mc)::value;
+    if constexpr (popc_c(M) == LEVEL) {
+      constexpr int SZ = G::size(M), O = G::off(M);
+#pragma unroll
+      for (int u = 0; u < G::slots(M); ++u) {
+        const int e = (int)threadIdx.x + 64 * u;
+        if (SZ % 64 == 0 || e < SZ) {
+          int dig[LEVEL];
+          fix_digits<LEVEL, G::LB>(e, dig);
+          lat[G::TOT + O + e] = lat[O + e] - fix_terms<S, B, LEVEL, M, REC>(lat, dig);
+        }
+      }
+    }
+  });
+}
+
+template <int S, int B, typename St, bool REC>
+__device__ void lattice_fix(const LatArgs& a, int64_t blk, double* lat) {
+  using G = LatFix<S, B>;
+  constexpr int NM = G::NM, FULL = G::FULL, BS = G::BS, TOT = G::TOT;
+  constexpr int NU = (BS + 63) / 64;      // own-block elements per lane
+  constexpr int PRE = NU < 4 ? NU : 4;    // of which prefetched
+  constexpr int GRP = 16;                 // staged values in flight per lane
+  const int tid = threadIdx.x;
+  const int32_t* rank = a.subrank + blk * NM;
+
+  const St* shi = (const St*)a.s_hi[S] + blk * BS;
+  const St* slo = (const St*)a.s_lo[S] + blk * BS;
+  double mpre[PRE];
+#pragma unroll
+  for (int u = 0; u < PRE; ++u) {
+    const int e = min(tid + 64 * u, BS - 1);
+    mpre[u] = ((double)shi[e] + (double)slo[e]) * a.inv_t;
+  }
+
+  // moments of every proper sub-block, GRP slots of 64 elements at a time
+  static_for<0, (G::NSLOT + GRP - 1) / GRP>([&](auto gc) __attribute__((always_inline)) {
+    constexpr int g0 = decltype(gc)::value * GRP;
+    constexpr int NG = G::NSLOT - g0 < GRP ? G::NSLOT - g0 : GRP;
+    double v[NG];
+    static_for<0, NG>([&](auto jc) __attribute__((always_inline)) {
+      constexpr int j = decltype(jc)::value;
+      constexpr int M = G::slot_mask(g0 + j), U = G::slot_index(g0 + j);
+      constexpr int s = popc_c(M), SZ = G::size(M);
+      const int64_t sb = (int64_t)rank[M] * SZ;
+      const int e = SZ % 64 == 0 ? tid + 64 * U : min(tid + 64 * U, SZ - 1);
+      v[j] = ((double)((const St*)a.s_hi[s])[sb + e] + (double)((const St*)a.s_lo[s])[sb + e]) * a.inv_t;
+    });
+    static_for<0, NG>([&](auto jc) __attribute__((always_inline)) {
+      constexpr int j = decltype(jc)::value;
+      constexpr int M = G::slot_mask(g0 + j), U = G::slot_index(g0 + j);
+      constexpr int SZ = G::size(M);
+      const int e = tid + 64 * U;
+      if (SZ % 64 == 0 || e < SZ) lat[G::off(M) + e] = v[j];
+    });
+  });
+  __syncthreads();
+  if constexpr (S >= 3) { fix_level<S, B, REC, 2>(lat); __syncthreads(); }
+  if constexpr (S >= 4) { fix_level<S, B, REC, 3>(lat); __syncthreads(); }
+
+  double sq[S + 1];
+#pragma unroll
+  for (int k = 0; k <= S; ++k) sq[k] = 0.0;
+  // the block's own order-S cumulants
+  double* Cout = a.C[S] + blk * BS;
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int e = tid + 64 * u;
+    if (BS % 64 == 0 || e < BS) {
+      int dig[S];
+      fix_digits<S, G::LB>(e, dig);
+      const double m = u < PRE ? mpre[u < PRE ? u : 0] : ((double)shi[e] + (double)slo[e]) * a.inv_t;
+      const double c = m - fix_terms<S, B, S, FULL, REC>(lat, dig);
+      Cout[e] = c;
+      sq[S] += c * c;
+    }
+  }
+  // the lower-order blocks this block is designated to write
+  const int des = a.desig[blk];
+  static_for<1, S>([&](auto sc) __attribute__((always_inline)) {
+    constexpr int s = decltype(sc)::value;
+    constexpr int M = (1 << s) - 1, SZ = G::size(M);
+    constexpr int O = (s == 1 ? 0 : TOT) + G::off(M);
+    if (des & (1 << s)) {
+      double* dst = a.C[s] + (int64_t)rank[M] * SZ;
+#pragma unroll
+      for (int u = 0; u < G::slots(M); ++u) {
+        const int e = tid + 64 * u;
+        if (SZ % 64 == 0 || e < SZ) {
+          const double c = lat[O + e];
+          dst[e] = c;
+          sq[s] += c * c;
+        }
+      }
+    }
+  });
+#pragma unroll
+  for (int k = 1; k <= S; ++k) {
+    if (k == S || (des & (1 << k))) {
+      const int64_t kb = (k == S) ? blk : (int64_t)rank[(1 << k) - 1];
+      const double w = a.mult[k][kb] * wave_sum(sq[k]);
+      if (tid == 0) a.partial[k][kb] = w;
+    }
+  }
+}
+
+template <int S, int B, typename St, bool REC>
+__global__ __launch_bounds__(64) void k_combine_lattice_fix(LatArgs a) {
+  extern __shared__ __attribute__((aligned(16))) double lat[];
+  lattice_fix<S, B, St, REC>(a, blockIdx.x, lat);
+}
+
+// b with a compile-time lattice for order S (its lattice fits the LDS budget).
+__host__ __device__ constexpr bool lat_fix_ok(int S, int b) {
+  return S >= 2 && S <= 4 && (b == 2 || b == 4 || b == 8);
+}
+
 template <int S, typename St, bool REC>
 __global__ __launch_bounds__(64) void k_combine_lattice(LatArgs a) {
   extern __shared__ __attribute__((aligned(16))) double lat[];
@@ -965,14 +1183,28 @@ __global__ __launch_bounds__(64) void k_combine_lattice_batch(const LatArgs* __r
     const int64_t w = items[i];
     const LatArgs& a = ctxs[w >> 40];
     const int64_t blk = w & ((int64_t(1) << 40) - 1);
-    if (a.rec) lattice_block<S, St, true>(a, blk, lat);
-    else lattice_block<S, St, false>(a, blk, lat);
+    bool done = false;
+    if constexpr (lat_fix_ok(S, 2)) {
+      static_for<1, 4>([&](auto lc) __attribute__((always_inline)) {
+        constexpr int B = 1 << decltype(lc)::value;
+        if (a.b == B) {
+          if (a.rec) lattice_fix<S, B, St, true>(a, blk, lat);
+          else lattice_fix<S, B, St, false>(a, blk, lat);
+          done = true;
+        }
+      });
+    }
+    if (!done) {
+      if (a.rec) lattice_block<S, St, true>(a, blk, lat);
+      else lattice_block<S, St, false>(a, blk, lat);
+    }
     __syncthreads();
   }
 }
 
 // Final norms (Alg. 5 with exponent 2, Eq. (mef)): fro[k] = sqrt(sum of the
-// order's block partials); nu[k] = fro[k] / fro[2]^(k/2) for k >= 3.  One
+// order's block partials); nu[k] = fro[k] / fro[2]^(k/2) for k >= 3 (NaN
+// when fro[2] = 0, e.g. a constant window).  One
 // workgroup of 1024 threads issues the loads of every order first, then
 // reduces all orders together in a fixed order (thread, wave butterfly, then
 // the 16 waves in index order): about one memory round trip.
@@ -1015,7 +1247,7 @@ __device__ void norms_block(const NormArgs& a) {
   __syncthreads();
   if (tid <= a.d) {
     a.out[tid] = tid == 0 ? __builtin_nan("") : fro[tid];
-    a.out[a.d + 1 + tid] = (tid >= 3) ? fro[tid] / pow(fro[2], 0.5 * tid) : __builtin_nan("");
+    a.out[a.d + 1 + tid] = (tid >= 3 && fro[2] > 0.0) ? fro[tid] / pow(fro[2], 0.5 * tid) : __builtin_nan("");
   }
 }
 
@@ -1113,9 +1345,11 @@ __device__ __forceinline__ void quad_issue(char* gbuf, const UpdArgs& a, const Q
   }
 }
 
-template <int P, int H, int MR, int STR>
+// TM x TN: the tile's 16 x 16 fragments that lie inside its pivot GEMM (a
+// ragged edge tile multiplies only those)
+template <int P, int H, int MR, int STR, int TM, int TN>
 __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
-  constexpr int TM = 2, TN = 2, NF = 4;
+  constexpr int NF = TM * TN;
   using T = typename Tr<P>::X;
   using Acc = typename Tr<P>::Acc;
   using A1 = typename Tr<P>::A1;
@@ -1258,7 +1492,8 @@ __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
   }
 
   // each tile's four row-group partials, summed in a fixed order (row group
-  // 0 + 1 + 2 + 3), then the compensated fold of every stored element
+  // 0 + 1 + 2 + 3), then the compensated fold of every stored element; every
+  // wave owns four fragment slots of the buffer whatever its tile's shape
   A1* red = (A1*)smem;
   A1* shi = (A1*)a.s_hi[K_ORD];
   A1* slo = (A1*)a.s_lo[K_ORD];
@@ -1281,7 +1516,7 @@ __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
     const int f = q / TN, g = q % TN;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      red[((tile * 4 + rg) * NF + q) * 256 + frag_row<P>(lane, r) * 16 + (lane & 15)] = acc[f][g][r];
+      red[((tile * 4 + rg) * 4 + q) * 256 + frag_row<P>(lane, r) * 16 + (lane & 15)] = acc[f][g][r];
   }
   __syncthreads();
 #pragma unroll
@@ -1291,8 +1526,8 @@ __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
     else off = elem_offset(j);
     if (off >= 0) {
       const int e = j * 256 + ltid;
-      const A1* rt = red + tile * 4 * NF * 256;
-      const A1 sum = ((rt[e] + rt[NF * 256 + e]) + rt[2 * NF * 256 + e]) + rt[3 * NF * 256 + e];
+      const A1* rt = red + tile * 4 * 4 * 256;
+      const A1 sum = ((rt[e] + rt[4 * 256 + e]) + rt[2 * 4 * 256 + e]) + rt[3 * 4 * 256 + e];
       A1 h, l, sn = A1(0);
       if constexpr (EPF) {
         h = ph[j];
@@ -1313,17 +1548,30 @@ __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
   }
 }
 
+template <int P, int H, int MR, int STR>
+__device__ __forceinline__ void upd_quad_shape(const UpdArgs& a, const UpdItem& it, char* smem) {
+  // empty padding tiles (M = N = 0) take the 1 x 1 shape
+  const bool m2 = it.M - it.r0 > 16, n2 = it.N - it.c0 > 16;
+  if (m2 && n2) upd_quad_body<P, H, MR, STR, 2, 2>(a, it, smem);
+  else if (m2) upd_quad_body<P, H, MR, STR, 2, 1>(a, it, smem);
+  else if (n2) upd_quad_body<P, H, MR, STR, 1, 2>(a, it, smem);
+  else upd_quad_body<P, H, MR, STR, 1, 1>(a, it, smem);
+}
+
+// Each tile's waves take the body of its order and shape; every body runs
+// the same chunk loop (same barriers), so the tiles of one workgroup may
+// differ in both.
 template <int P, int STR, int KMAX>
 __global__ __launch_bounds__(1024) void k_update_quad(UpdArgs a) {
   __shared__ __attribute__((aligned(16))) char smem[QuadGeom<P, STR>::SMEM];
   const UpdItem it = a.items[blockIdx.x * 4 + (threadIdx.x >> 8)];
   switch (it.k) {
-    case 1: upd_quad_body<P, 1, 0, STR>(a, it, smem); break;
-    case 2: upd_quad_body<P, 1, 1, STR>(a, it, smem); break;
-    case 3: upd_quad_body<P, 2, 1, STR>(a, it, smem); break;
-    case 4: upd_quad_body<P, 2, 2, STR>(a, it, smem); break;
-    case 5: if constexpr (KMAX >= 5) upd_quad_body<P, 3, 2, STR>(a, it, smem); break;
-    case 6: if constexpr (KMAX >= 6) upd_quad_body<P, 3, 3, STR>(a, it, smem); break;
+    case 1: upd_quad_shape<P, 1, 0, STR>(a, it, smem); break;
+    case 2: upd_quad_shape<P, 1, 1, STR>(a, it, smem); break;
+    case 3: upd_quad_shape<P, 2, 1, STR>(a, it, smem); break;
+    case 4: upd_quad_shape<P, 2, 2, STR>(a, it, smem); break;
+    case 5: if constexpr (KMAX >= 5) upd_quad_shape<P, 3, 2, STR>(a, it, smem); break;
+    case 6: if constexpr (KMAX >= 6) upd_quad_shape<P, 3, 3, STR>(a, it, smem); break;
     default: break;
   }
 }
@@ -1534,8 +1782,29 @@ static hipError_t launch_lattice_s(bool rec, const LatArgs& a, int64_t nblocks, 
   return hipGetLastError();
 }
 
+template <int S, int B, typename St>
+static hipError_t launch_lattice_fix(bool rec, const LatArgs& a, int64_t nblocks, size_t lds, hipStream_t st) {
+  if (rec) hipLaunchKernelGGL((k_combine_lattice_fix<S, B, St, true>), dim3((unsigned)nblocks), dim3(64), lds, st, a);
+  else hipLaunchKernelGGL((k_combine_lattice_fix<S, B, St, false>), dim3((unsigned)nblocks), dim3(64), lds, st, a);
+  return hipGetLastError();
+}
+
 template <typename St>
 static hipError_t launch_lattice_t(int d, bool rec, const LatArgs& a, int64_t nblocks, size_t lds, hipStream_t st) {
+  if (lat_fix_ok(d, a.b)) {
+    switch (d * 16 + a.b) {
+      case 2 * 16 + 2: return launch_lattice_fix<2, 2, St>(rec, a, nblocks, lds, st);
+      case 2 * 16 + 4: return launch_lattice_fix<2, 4, St>(rec, a, nblocks, lds, st);
+      case 2 * 16 + 8: return launch_lattice_fix<2, 8, St>(rec, a, nblocks, lds, st);
+      case 3 * 16 + 2: return launch_lattice_fix<3, 2, St>(rec, a, nblocks, lds, st);
+      case 3 * 16 + 4: return launch_lattice_fix<3, 4, St>(rec, a, nblocks, lds, st);
+      case 3 * 16 + 8: return launch_lattice_fix<3, 8, St>(rec, a, nblocks, lds, st);
+      case 4 * 16 + 2: return launch_lattice_fix<4, 2, St>(rec, a, nblocks, lds, st);
+      case 4 * 16 + 4: return launch_lattice_fix<4, 4, St>(rec, a, nblocks, lds, st);
+      case 4 * 16 + 8: return launch_lattice_fix<4, 8, St>(rec, a, nblocks, lds, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (d) {
     case 1: return launch_lattice_s<1, St>(rec, a, nblocks, lds, st);
     case 2: return launch_lattice_s<2, St>(rec, a, nblocks, lds, st);

@@ -185,6 +185,35 @@ std::vector<UpdItem> build_items(const Tables& T, int kmin, int kmax, int tile_r
   return items;
 }
 
+std::vector<UpdItem> pack_quads(const std::vector<UpdItem>& items) {
+  if (items.empty()) return {};
+  auto cost = [](const UpdItem& it) {
+    const int fm = it.M - it.r0 > 16 ? 2 : 1, fn = it.N - it.c0 > 16 ? 2 : 1;
+    return fm * fn;
+  };
+  std::vector<size_t> order(items.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](size_t x, size_t y) { return cost(items[x]) > cost(items[y]); });
+  const size_t ng = (items.size() + 3) / 4;
+  std::vector<int> load(ng, 0), fill(ng, 0);
+  std::vector<UpdItem> out(ng * 4);
+  UpdItem empty = items[0];
+  empty.M = 0;
+  empty.N = 0;
+  for (size_t g = 0; g < ng; ++g)
+    for (int j = 0; j < 4; ++j) out[g * 4 + (size_t)j] = empty;
+  for (size_t i : order) {
+    size_t best = ng;
+    for (size_t g = 0; g < ng; ++g)
+      if (fill[g] < 4 && (best == ng || load[g] < load[best])) best = g;
+    out[best * 4 + (size_t)fill[best]] = items[i];
+    ++fill[best];
+    load[best] += cost(items[i]);
+  }
+  return out;
+}
+
 int64_t coverage(const Tables& T, int k, std::vector<int32_t>& hits) {
   const OrderInfo& o = T.ord[k];
   hits.assign((size_t)o.nelems, 0);

@@ -32,6 +32,13 @@ int64_t binom(int64_t a, int64_t k);
 int64_t ipow64(int64_t b, int k);
 int build_tables(int n, int b, int d, Tables& T);
 std::vector<UpdItem> build_items(const Tables& T, int kmin, int kmax, int tile_rows, int tile_cols);
+
+// The 32 x 32 tiles of build_items in groups of four (one workgroup of the
+// four-tile update each), padded with empty tiles (M = N = 0).  A tile costs
+// its 16 x 16 fragments inside the pivot GEMM; groups are filled longest
+// first, each tile to the open group with the least cost so far, so the
+// dearest group (the launch's critical path) stays close to the average.
+std::vector<UpdItem> pack_quads(const std::vector<UpdItem>& items);
 // Counts how often every stored order-k element is produced by the pivot
 // tables; returns the number of (pivot, row, column) triples that land
 // outside the pyramid or on an element with different global indices.
