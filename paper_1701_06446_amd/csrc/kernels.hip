@@ -1368,33 +1368,51 @@ __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
   const int ncp = (a.np + R - 1) / R;
   const int nch = ncp + (a.nm + R - 1) / R;
 
+  char* gbuf = smem + 2 * rg * G::BUFB;
+
+  // k-step s of lane group q = lane / 16 reads row 4 s + q: single-address
+  // LDS reads whose k-step offsets all fit the 16-bit immediate, so no
+  // address register is spent per k-step
+  const int lrow = lane >> 4;
+  const int lbase = 2 * rg * G::BUFB;
+  // f32: the element offsets are found before the main loop and the running
+  // sums are loaded during the last chunk; f64 finds and loads them after
+  // the loop (held through it they would push the allocation past 128
+  // registers into scratch)
+  constexpr bool EPF = P == PREC_F32;
+  constexpr int NE = EPF ? NF : 1;
+  // the tile's table entries are requested before chunk 0's copy, so that
+  // waiting for them does not wait for the copy as well; empty tiles (the
+  // launch's padding) have M = N = 0 and read row/column 0
+  LeftCol La[TM], Le[NE];
+  RightCol Rb[TN], Re[NE];
+#pragma unroll
+  for (int f = 0; f < TM; ++f) La[f] = left[it.lrow0 + max(0, min(it.r0 + 16 * f + (lane & 15), it.M - 1))];
+#pragma unroll
+  for (int g = 0; g < TN; ++g) Rb[g] = right[it.rcol0 + max(0, min(it.c0 + 16 * g + (lane & 15), it.N - 1))];
+  if constexpr (EPF) {
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+      const int f = j / TN, g = j % TN;
+      Le[j] = left[it.lrow0 + max(0, min(it.r0 + 16 * f + ((ltid >> 4) & 15), it.M - 1))];
+      Re[j] = right[it.rcol0 + max(0, min(it.c0 + 16 * g + (ltid & 15), it.N - 1))];
+    }
+  }
   QuadLanes<P, STR> ql;
   quad_lanes<P, STR>(ql, a.n, tile);
-  char* gbuf = smem + 2 * rg * G::BUFB;
   quad_issue<P, STR>(gbuf, a, ql, 0, ncp, rg, tile);
 
-  const int lrow = (NKS % 2 == 0) ? 2 * (lane >> 4) : (lane >> 4);
-  const int lbase = 2 * rg * G::BUFB;
-  // empty tiles (the launch's padding) have M = N = 0 and read row/column 0
   int ao[TM][H];
   int bo[TN][MRC];
 #pragma unroll
-  for (int f = 0; f < TM; ++f) {
-    const int r = max(0, min(it.r0 + 16 * f + (lane & 15), it.M - 1));
-    const LeftCol L = left[it.lrow0 + r];
+  for (int f = 0; f < TM; ++f)
 #pragma unroll
-    for (int q = 0; q < H; ++q) ao[f][q] = lbase + (lrow * STR + (L.c[q] < a.n ? L.c[q] : 0)) * ES;
-  }
+    for (int q = 0; q < H; ++q) ao[f][q] = lbase + (lrow * STR + (La[f].c[q] < a.n ? La[f].c[q] : 0)) * ES;
 #pragma unroll
-  for (int g = 0; g < TN; ++g) {
-    const int c = max(0, min(it.c0 + 16 * g + (lane & 15), it.N - 1));
-    const RightCol Rc = right[it.rcol0 + c];
+  for (int g = 0; g < TN; ++g)
 #pragma unroll
-    for (int q = 0; q < MRC; ++q) bo[g][q] = lbase + (lrow * STR + ((q < MR && Rc.c[q] < a.n) ? Rc.c[q] : 0)) * ES;
-  }
-  // (the element offsets are found after the main loop: held through it they
-  // would push the allocation past 128 registers into scratch)
-  constexpr bool EPF = false;
+    for (int q = 0; q < MRC; ++q)
+      bo[g][q] = lbase + (lrow * STR + ((q < MR && Rb[g].c[q] < a.n) ? Rb[g].c[q] : 0)) * ES;
   auto elem_offset = [&](int j) __attribute__((always_inline)) -> int64_t {
     const int f = j / TN, g = j - (j / TN) * TN;
     const int r = it.r0 + 16 * f + ((ltid >> 4) & 15), c = it.c0 + 16 * g + (ltid & 15);
@@ -1411,7 +1429,16 @@ __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
   int64_t eoff[NF];
   if constexpr (EPF) {
 #pragma unroll
-    for (int j = 0; j < NF; ++j) eoff[j] = elem_offset(j);
+    for (int j = 0; j < NF; ++j) {
+      const int f = j / TN, g = j % TN;
+      const int r = it.r0 + 16 * f + ((ltid >> 4) & 15), c = it.c0 + 16 * g + (ltid & 15);
+      bool pad = r >= it.M || c >= it.N;
+#pragma unroll
+      for (int q = 0; q < H; ++q) pad = pad || Le[j].c[q] >= a.n;
+#pragma unroll
+      for (int q = 0; q < MR; ++q) pad = pad || Re[j].c[q] >= a.n;
+      eoff[j] = pad ? -1 : Le[j].base + Re[j].base;
+    }
   }
 
   Acc acc[TM][TN];
@@ -1428,7 +1455,7 @@ __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
     constexpr int NB = PIPE ? 2 : 1;
     T fa[NB][TM][H], fb[NB][TN][MRC];
     auto load_factors = [&](int st, int buf) __attribute__((always_inline)) {
-      const int so = koff<NKS, STR, ES>(st) + BO;
+      const int so = 4 * st * STR * ES + BO;
 #pragma unroll
       for (int f = 0; f < TM; ++f)
 #pragma unroll
@@ -1444,6 +1471,9 @@ __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
       const int cur = PIPE ? (st & 1) : 0;
       if (PIPE && st + 1 < NKS) load_factors(st + 1, cur ^ 1);
       if (!PIPE && st > 0) load_factors(st, 0);
+      // the next k-step's LDS reads stay ahead of this k-step's products
+      // (left alone, the scheduler sinks each read to its use)
+      if constexpr (PIPE) __builtin_amdgcn_sched_barrier(0);
       T A[TM], B[TN];
 #pragma unroll
       for (int f = 0; f < TM; ++f) {
@@ -1469,10 +1499,28 @@ __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
     }
   };
 
+  A1* shi = (A1*)a.s_hi[K_ORD];
+  A1* slo = (A1*)a.s_lo[K_ORD];
+  A1* snp = (A1*)a.snap[K_ORD];
+  A1 ph[NF], pl[NF], ps[NF];
+  auto load_state = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+      ph[j] = pl[j] = ps[j] = A1(0);
+      if (eoff[j] >= 0) {
+        ph[j] = shi[eoff[j]];
+        pl[j] = slo[eoff[j]];
+        if (a.fifo == 2) ps[j] = snp[eoff[j]];
+      }
+    }
+  };
+
   auto run_chunk = [&](int ci) __attribute__((always_inline)) {
     __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
     __syncthreads();
     if (ci + 1 < nch) quad_issue<P, STR>(gbuf + ((ci + 1) & 1) * G::BUFB, a, ql, ci + 1, ncp, rg, tile);
+    if constexpr (EPF)
+      if (ci + 1 == nch) load_state();  // arrives during the last chunk's k-steps
     if (ci & 1) multiply_chunk(IntC<G::BUFB>{});
     else multiply_chunk(IntC<0>{});
   };
@@ -1495,21 +1543,8 @@ __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
   // 0 + 1 + 2 + 3), then the compensated fold of every stored element; every
   // wave owns four fragment slots of the buffer whatever its tile's shape
   A1* red = (A1*)smem;
-  A1* shi = (A1*)a.s_hi[K_ORD];
-  A1* slo = (A1*)a.s_lo[K_ORD];
-  A1* snp = (A1*)a.snap[K_ORD];
-  A1 ph[NF], pl[NF], ps[NF];
-  if constexpr (EPF) {
-#pragma unroll
-    for (int j = 0; j < NF; ++j) {
-      ph[j] = pl[j] = ps[j] = A1(0);
-      if (eoff[j] >= 0) {
-        ph[j] = shi[eoff[j]];
-        pl[j] = slo[eoff[j]];
-        if (a.fifo == 2) ps[j] = snp[eoff[j]];
-      }
-    }
-  }
+  if constexpr (EPF)
+    if (nch == 0) load_state();
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < NF; ++q) {
@@ -1564,7 +1599,9 @@ __device__ __forceinline__ void upd_quad_shape(const UpdArgs& a, const UpdItem& 
 template <int P, int STR, int KMAX>
 __global__ __launch_bounds__(1024) void k_update_quad(UpdArgs a) {
   __shared__ __attribute__((aligned(16))) char smem[QuadGeom<P, STR>::SMEM];
-  const UpdItem it = a.items[blockIdx.x * 4 + (threadIdx.x >> 8)];
+  // the item's address is uniform per wave: a scalar load
+  const int tile = __builtin_amdgcn_readfirstlane(threadIdx.x >> 8);
+  const UpdItem it = a.items[blockIdx.x * 4 + tile];
   switch (it.k) {
     case 1: upd_quad_shape<P, 1, 0, STR>(a, it, smem); break;
     case 2: upd_quad_shape<P, 1, 1, STR>(a, it, smem); break;
