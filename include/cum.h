@@ -172,6 +172,14 @@ int cum_norms_device(cum_ctx *ctx, const double **dev_ptr);
 int cum_profile_enable(cum_ctx *ctx, int on);
 
 /*
+ * cum_profile_sample -- bracket only the first of every `every` launches of
+ * each selected class (every >= 1; cum_profile_enable resets it to 1), so
+ * that a long timed run pays for few event pairs.  Returns CUM_EINVAL for
+ * every < 1.  Does not synchronise.
+ */
+int cum_profile_sample(cum_ctx *ctx, int every);
+
+/*
  * cum_profile_read -- per kernel class (0 = moment update, 1 = cumulant
  * combine, 2 = norms): launches[3] and total_ms[3] of the launches recorded
  * since profiling was enabled or last read; clears the records.

@@ -35,7 +35,7 @@ EXPORTS = ("cum_init", "cum_update", "cum_get", "cum_get_moments", "cum_norms",
            "cum_profile_enable", "cum_profile_read", "cum_batch_create", "cum_batch_update",
            "cum_batch_sync", "cum_batch_free", "cum_loss_grad",
            "cum_init_fifo", "cum_set_combine", "cum_recompute", "cum_loss_plan_create",
-           "cum_loss_plan_grad", "cum_loss_plan_free")
+           "cum_loss_plan_grad", "cum_loss_plan_free", "cum_profile_sample")
 
 
 class CumError(RuntimeError):
@@ -69,6 +69,7 @@ def _load():
         "cum_plan_coverage": (i64, [i32, i32, i32, ctypes.POINTER(ctypes.c_int32)]),
         "cum_plan_items": (i64, [i32, i32, i32]),
         "cum_profile_enable": (i32, [vp, i32]),
+        "cum_profile_sample": (i32, [vp, i32]),
         "cum_batch_create": (i32, [ctypes.POINTER(vp), ctypes.POINTER(vp), i32]),
         "cum_batch_update": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64)]),
         "cum_batch_sync": (i32, [vp]),
@@ -259,9 +260,10 @@ def cum_plan_items(n: int, d: int, b: int) -> int:
 PROFILE_CLASSES = {"update": 1, "combine": 2, "norms": 4}
 
 
-def cum_profile_enable(ctx: Context, on=True):
+def cum_profile_enable(ctx: Context, on=True, every: int = 1):
     """on: True (every kernel class), False, or an iterable of class names
-    ("update", "combine", "norms") to bracket with HIP events."""
+    ("update", "combine", "norms") to bracket with HIP events; every: bracket
+    one launch in that many per class."""
     if on is True:
         mask = 7
     elif not on:
@@ -271,6 +273,8 @@ def cum_profile_enable(ctx: Context, on=True):
         for name in on:
             mask |= PROFILE_CLASSES[name]
     _check(_lib.cum_profile_enable(ctx.handle, mask), "cum_profile_enable")
+    if every != 1:
+        _check(_lib.cum_profile_sample(ctx.handle, int(every)), "cum_profile_sample")
 
 
 def cum_profile_read(ctx: Context):

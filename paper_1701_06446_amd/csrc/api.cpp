@@ -75,6 +75,8 @@ struct cum_ctx {
   int lat_off[(1 << CUM_MAXD) + 1] = {};
   int combine = CUM_COMBINE_PARTITIONS;
   int profile_mask = 0;
+  int profile_every = 1;              // bracket one launch in this many per class
+  int64_t profile_seen[3] = {0, 0, 0};
   struct Ev { int cls; hipEvent_t a, b; };
   std::vector<Ev> events;
   std::vector<hipEvent_t> event_pool;
@@ -186,6 +188,7 @@ struct Timed {
   hipEvent_t a = nullptr, b = nullptr;
   Timed(cum_ctx* ctx, int k) : c(ctx), cls(k) {
     if (!(c->profile_mask & (1 << cls))) return;
+    if (c->profile_seen[cls]++ % c->profile_every != 0) return;
     a = pooled_event(c);
     b = pooled_event(c);
     if (!a || !b) {
@@ -673,6 +676,16 @@ int cum_profile_enable(cum_ctx* c, int on) {
   CUM_TRY(hipStreamSynchronize(c->stream));
   drop_events(c);
   c->profile_mask = on & 7;
+  c->profile_every = 1;
+  for (int q = 0; q < 3; ++q) c->profile_seen[q] = 0;
+  return CUM_OK;
+}
+
+int cum_profile_sample(cum_ctx* c, int every) {
+  if (!c || every < 1) return CUM_EINVAL;
+  if (!c->ready) return CUM_ESTATE;
+  c->profile_every = every;
+  for (int q = 0; q < 3; ++q) c->profile_seen[q] = 0;
   return CUM_OK;
 }
 

@@ -172,3 +172,25 @@ def test_memory_cap_gives_enomem(monkeypatch):
     with pytest.raises(cum.CumError) as e:
         cum.cum_init(8, 3, 2, rows, prec="fp32")
     assert e.value.status == cum.CUM_ENOMEM
+
+
+def test_profile_sampling_counts():
+    """cum_profile_sample: only the first of every `every` launches of a class
+    is bracketed; every < 1 is rejected; cum_profile_enable resets it."""
+    import paper_1701_06446_amd as cum
+
+    rows = as_input(_rows(3, 400 + 9 * 20, 12), "fp32")
+    dev = to_device(rows)
+    ctx = cum.cum_init(12, 3, 2, dev[:400], prec="fp32")
+    cum.cum_profile_enable(ctx, ["update", "combine"], every=3)
+    for w in range(1, 8):
+        cum.cum_update(ctx, dev[400 + (w - 1) * 20:400 + w * 20], dev[(w - 1) * 20:w * 20])
+    prof = cum.cum_profile_read(ctx)
+    assert prof["update"][0] == 3 and prof["combine"][0] == 3 and prof["norms"][0] == 0
+    assert all(v[1] > 0 for k, v in prof.items() if k != "norms")
+    assert cum._lib.cum_profile_sample(ctx.handle, 0) == cum.CUM_EINVAL
+    cum.cum_profile_enable(ctx, ["update"])
+    cum.cum_update(ctx, dev[540:560], dev[140:160])
+    cum.cum_update(ctx, dev[560:580], dev[160:180])
+    assert cum.cum_profile_read(ctx)["update"][0] == 2
+    cum.cum_free(ctx)
