@@ -130,6 +130,9 @@ def run_path(path, s, warmup, steps, check, host_leg=False):
     t0 = time.perf_counter()
     for _ in range(steps):
         step()
+    # every step's norms are formed inside the timed region: each update
+    # launch forms the previous step's, cum_sync the last one
+    cum.cum_sync(ctx)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = cum.cum_profile_read(ctx)
@@ -139,6 +142,7 @@ def run_path(path, s, warmup, steps, check, host_leg=False):
     t1 = time.perf_counter()
     for _ in range(steps):
         step()
+    cum.cum_sync(ctx)
     torch.cuda.synchronize()
     plain = time.perf_counter() - t1
     cum.cum_profile_enable(ctx, True)
@@ -176,6 +180,7 @@ def run_path(path, s, warmup, steps, check, host_leg=False):
     t2 = time.perf_counter()
     for _ in range(5):
         cum.cum_recompute(ctx, win)
+    cum.cum_sync(ctx)  # the last recalculation's norms
     torch.cuda.synchronize()
     rec_ms = (time.perf_counter() - t2) / 5 * 1e3
     out["recompute_ms"] = rec_ms
@@ -289,6 +294,7 @@ def run_order6(steps=4, warmup=1):
     t1 = time.perf_counter()
     for _ in range(steps):
         step()
+    cum.cum_sync(ctx)  # the last step's norms
     torch.cuda.synchronize()
     el = time.perf_counter() - t1
     prof = cum.cum_profile_read(ctx)

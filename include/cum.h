@@ -94,7 +94,10 @@ int cum_init(cum_ctx **ctx, int n, int d, int b, const void *X, int64_t t, int p
  * cum_update -- slide the window by p rows: M_k += (sum over X_new of x^(k) -
  * sum over X_old of x^(k)) / t for k = 1..d (Eq. (momupdate), Alg. 2), then
  * recompute C_1..C_d (Alg. 3/4) and the norms (Alg. 5, Eq. (mef)).
- * Asynchronous on the context's stream.
+ * Asynchronous on the context's stream.  The norms' final reduction is
+ * deferred: the next update launch forms it in one extra workgroup on a CU
+ * its tiles leave idle, and cum_norms, cum_norms_device and cum_sync launch
+ * it on its own if it is still pending.
  *   X_new  p x n rows entering the window
  *   X_old  p x n rows leaving it; precondition (not checked): these are the
  *          window's p oldest rows
@@ -156,9 +159,11 @@ int cum_norms(cum_ctx *ctx, double *fro, double *nu);
 
 /*
  * cum_norms_device -- device address of the norms written by the last
- * init/update: 2(d+1) doubles, fro[0..d] then nu[0..d].  Does not
- * synchronise; the buffer is owned by the context and overwritten by the
- * next update.
+ * init/update: 2(d+1) doubles, fro[0..d] then nu[0..d].  Enqueues their
+ * final reduction on the context's stream if it is still pending, so work
+ * enqueued on that stream afterwards reads them; call it after every update
+ * whose norms are read on the device.  Does not synchronise; the buffer is
+ * owned by the context and overwritten by the next update.
  */
 int cum_norms_device(cum_ctx *ctx, const double **dev_ptr);
 
@@ -206,7 +211,8 @@ int cum_profile_read(cum_ctx *ctx, int64_t *launches, double *total_ms);
 enum { CUM_COMBINE_PARTITIONS = 0, CUM_COMBINE_RECURSION = 1 };
 int cum_set_combine(cum_ctx *ctx, int method);
 
-/* cum_sync -- wait for all work queued on the context's stream. */
+/* cum_sync -- finish the context's work: launch the last update's norms if
+ * still pending, then wait for everything queued on the context's stream. */
 int cum_sync(cum_ctx *ctx);
 
 /* cum_free -- release the context and its device state; NULL is allowed. */

@@ -74,6 +74,10 @@ struct cum_ctx {
   size_t lat_lds = 0;
   int lat_off[(1 << CUM_MAXD) + 1] = {};
   int combine = CUM_COMBINE_PARTITIONS;
+  // norms of the last combine not yet formed: the next update launch forms
+  // them in one extra workgroup, or flush_norms launches them alone
+  bool norms_pending = false;
+  NormArgs pending_na{};
   int profile_mask = 0;
   int profile_every = 1;              // bracket one launch in this many per class
   int64_t profile_seen[3] = {0, 0, 0};
@@ -255,6 +259,12 @@ int run_contraction(cum_ctx* c, const char* xp, int64_t np, const char* xm, int6
     a.vec = ((c->n * c->x_size) % 16 == 0) && ((uintptr_t)a.xp % 16 == 0) && ((uintptr_t)a.xm % 16 == 0);
     a.quad = c->quad && a.vec;
     a.items = a.quad ? c->qitems : c->items;
+    a.with_norms = 0;
+    if (c->norms_pending && c->nitems > 0) {
+      a.with_norms = 1;
+      a.na = c->pending_na;
+      c->norms_pending = false;
+    }
     Timed tm(c, 0);
     CUM_TRY(launch_update(c->prec, c->tm, c->tn, c->d, a, c->nitems, c->stream));
   }
@@ -312,8 +322,18 @@ int run_combine_and_norms(cum_ctx* c) {
     na.partial[k] = c->partial[k];
   }
   na.out = c->norms;
+  // formed by the next update launch (on an idle CU) or by flush_norms
+  c->pending_na = na;
+  c->norms_pending = true;
+  return CUM_OK;
+}
+
+// Launches the pending norms on their own (before anything reads them).
+int flush_norms(cum_ctx* c) {
+  if (!c->norms_pending) return CUM_OK;
+  c->norms_pending = false;
   Timed tm(c, 2);
-  CUM_TRY(launch_norms(na, c->stream));
+  CUM_TRY(launch_norms(c->pending_na, c->stream));
   return CUM_OK;
 }
 
@@ -645,6 +665,7 @@ int cum_norms(cum_ctx* c, double* fro, double* nu) {
   if (!c->ready) return CUM_ESTATE;
   if (!fro || !nu) return CUM_EINVAL;
   CUM_TRY(wait_batch(c));
+  if (int rc = flush_norms(c)) return rc;
   CUM_TRY(hipStreamSynchronize(c->stream));
   std::vector<double> h((size_t)2 * (c->d + 1));
   CUM_TRY(hipMemcpy(h.data(), c->norms, h.size() * 8, hipMemcpyDeviceToHost));
@@ -658,6 +679,7 @@ int cum_norms(cum_ctx* c, double* fro, double* nu) {
 int cum_norms_device(cum_ctx* c, const double** dev_ptr) {
   if (!c || !dev_ptr) return CUM_EINVAL;
   if (!c->ready) return CUM_ESTATE;
+  if (int rc = flush_norms(c)) return rc;
   *dev_ptr = c->norms;
   return CUM_OK;
 }
@@ -666,6 +688,7 @@ int cum_sync(cum_ctx* c) {
   if (!c) return CUM_EINVAL;
   if (!c->ready) return CUM_ESTATE;
   CUM_TRY(wait_batch(c));
+  if (int rc = flush_norms(c)) return rc;
   CUM_TRY(hipStreamSynchronize(c->stream));
   return CUM_OK;
 }
@@ -972,6 +995,11 @@ int cum_batch_update(cum_batch* bt, const void* const* X_new, const void* const*
       if (vl && (((uintptr_t)X_new[i] | (uintptr_t)xo) % 16)) return CUM_EINVAL;
     }
   }
+  for (cum_ctx* c : bt->ctx)
+    if (c->norms_pending) {  // the batch step rewrites the partials they need
+      if (int rc = flush_norms(c)) return rc;
+      c->direct_since_batch = true;
+    }
   for (cum_ctx* c : bt->ctx)
     if (c->direct_since_batch) {
       CUM_TRY(hipStreamSynchronize(c->stream));

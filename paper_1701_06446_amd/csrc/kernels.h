@@ -16,6 +16,14 @@ constexpr int UPD_X_BYTES = 32768;     // bytes of data rows per LDS chunk
 constexpr int UPD_DIRECT_BYTES = 17408; // bytes per buffer of the double-buffered direct path
 constexpr int UPD_ZERO_BYTES = 256;     // zeroed device block the direct path reads for padding
 
+struct NormArgs {
+  int d;
+  int kfirst;               // orders below kfirst already hold their norm in out[] (1: none)
+  int64_t nblocks[CUM_MAXD + 1];
+  const double* partial[CUM_MAXD + 1];
+  double* out;              // [0..d] ||C_k||_F, [d+1 .. 2d+1] nu_k
+};
+
 struct UpdArgs {
   const void* xp;           // rows entering the window (+1), row-major np x n
   const void* xm;           // rows leaving the window (-1), row-major nm x n
@@ -33,6 +41,10 @@ struct UpdArgs {
   // snap; 2 fold the increment, fold out the one stored in snap, store it
   int fifo;
   void* snap[CUM_MAXD + 1]; // this update's FIFO slot, one value per stored element
+  // 1: one extra workgroup (the last) finishes the norms of the previous
+  // combine from its block partials, on a CU the tiles leave idle
+  int with_norms;
+  NormArgs na;
 };
 
 // LDS budget for a combine block's staged lower-order sub-blocks.
@@ -78,13 +90,6 @@ struct LatArgs {
 // (b+1)^d - 1 - b^d elements of the proper sub-blocks.
 size_t lattice_lds_bytes(int d, int b);
 
-struct NormArgs {
-  int d;
-  int kfirst;               // orders below kfirst already hold their norm in out[] (1: none)
-  int64_t nblocks[CUM_MAXD + 1];
-  const double* partial[CUM_MAXD + 1];
-  double* out;              // [0..d] ||C_k||_F, [d+1 .. 2d+1] nu_k
-};
 
 bool update_tile_supported(int tm, int tn);
 bool update_quad_supported(int prec, int n);

@@ -22,6 +22,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
+__device__ __forceinline__ void norms_block(const NormArgs& a);
+
 template <int P> struct Tr;
 template <> struct Tr<PREC_F64> {
   using X = double; using Acc = f64x4; using A1 = double;
@@ -610,6 +612,10 @@ template <int P, int TM, int TN, int STR, bool VL, int KMAX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_BF16X3 ? 1 : 4))) void k_update(
     UpdArgs a) {
   __shared__ __attribute__((aligned(16))) char smem[upd_smem_bytes<P, STR, VL>()];
+  if (a.with_norms && blockIdx.x == gridDim.x - 1) {
+    norms_block(a.na);
+    return;
+  }
   const UpdItem it = a.items[blockIdx.x];
   upd_dispatch<P, TM, TN, STR, VL, KMAX>(a, it, smem);
 }
@@ -1207,11 +1213,14 @@ __global__ __launch_bounds__(64) void k_combine_lattice_batch(const LatArgs* __r
 // when fro[2] = 0, e.g. a constant window).  One
 // workgroup of 1024 threads issues the loads of every order first, then
 // reduces all orders together in a fixed order (thread, wave butterfly, then
-// the 16 waves in index order): about one memory round trip.
-__device__ void norms_block(const NormArgs& a) {
+// the waves in index order): about one memory round trip.  Any block size
+// that is a multiple of 64 up to 1024 (the 1024-thread form is the launch of
+// its own; an update launch may carry it as one extra workgroup).
+__device__ __forceinline__ void norms_block(const NormArgs& a) {
   __shared__ double red[CUM_MAXD + 1][16];
   __shared__ double fro[CUM_MAXD + 1];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nt = blockDim.x, nw = nt >> 6;
   double s[CUM_MAXD + 1];
 #pragma unroll
   for (int k = 1; k <= CUM_MAXD; ++k) {
@@ -1222,11 +1231,11 @@ __device__ void norms_block(const NormArgs& a) {
       double v[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int64_t i = tid + 1024 * u;
+        const int64_t i = tid + (int64_t)nt * u;
         v[u] = i < nb ? p[i] : 0.0;
       }
       s[k] = (v[0] + v[1]) + (v[2] + v[3]);
-      for (int64_t i = tid + 4096; i < nb; i += 1024) s[k] += p[i];
+      for (int64_t i = tid + 4 * (int64_t)nt; i < nb; i += nt) s[k] += p[i];
     }
   }
 #pragma unroll
@@ -1240,7 +1249,7 @@ __device__ void norms_block(const NormArgs& a) {
       fro[tid] = a.out[tid];  // written by the small-order kernel
     } else {
       double t = 0.0;
-      for (int w = 0; w < 16; ++w) t += red[tid][w];
+      for (int w = 0; w < nw; ++w) t += red[tid][w];
       fro[tid] = sqrt(t);
     }
   }
@@ -1599,6 +1608,10 @@ __device__ __forceinline__ void upd_quad_shape(const UpdArgs& a, const UpdItem& 
 template <int P, int STR, int KMAX>
 __global__ __launch_bounds__(1024) void k_update_quad(UpdArgs a) {
   __shared__ __attribute__((aligned(16))) char smem[QuadGeom<P, STR>::SMEM];
+  if (a.with_norms && blockIdx.x == gridDim.x - 1) {
+    norms_block(a.na);
+    return;
+  }
   // the item's address is uniform per wave: a scalar load
   const int tile = __builtin_amdgcn_readfirstlane(threadIdx.x >> 8);
   const UpdItem it = a.items[blockIdx.x * 4 + tile];
@@ -1659,14 +1672,15 @@ static void launch_kmax(int kmax, const UpdArgs& a, int nitems, hipStream_t st) 
   if constexpr (VL && P != PREC_BF16X3 && QuadGeom<P, STR>::OK) {
     if (a.quad) {
       // a.items holds nitems rounded up to whole groups of four
-      const dim3 grid((unsigned)((nitems + 3) / 4));
+      const dim3 grid((unsigned)((nitems + 3) / 4 + (a.with_norms ? 1 : 0)));
       if (kmax <= 4) hipLaunchKernelGGL((k_update_quad<P, STR, 4>), grid, dim3(1024), 0, st, a);
       else hipLaunchKernelGGL((k_update_quad<P, STR, 6>), grid, dim3(1024), 0, st, a);
       return;
     }
   }
-  if (kmax <= 4) hipLaunchKernelGGL((k_update<P, 2, 2, STR, VL, 4>), dim3(nitems), dim3(256), 0, st, a);
-  else hipLaunchKernelGGL((k_update<P, 2, 2, STR, VL, 6>), dim3(nitems), dim3(256), 0, st, a);
+  const dim3 grid((unsigned)(nitems + (a.with_norms ? 1 : 0)));
+  if (kmax <= 4) hipLaunchKernelGGL((k_update<P, 2, 2, STR, VL, 4>), grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((k_update<P, 2, 2, STR, VL, 6>), grid, dim3(256), 0, st, a);
 }
 
 // Whether launch_update takes the four-tiles-per-workgroup kernel for this
