@@ -1289,7 +1289,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_B
 }
 
 // ---------------------------------------------------------------------------
-// Four tiles per workgroup (f32/f64 rows of 16-byte multiples): 16 waves,
+// Four tiles per workgroup (f32/f64/split-bf16 rows of 16-byte multiples): 16 waves,
 // wave w works on tile w / 4 with row group w % 4 of every chunk.  A row
 // group's rows are copied into LDS once (the four waves that use them split
 // the copy) and read by all four tiles, so each chunk row crosses a CU's
@@ -1310,7 +1310,7 @@ template <int P, int STR> struct QuadGeom {
   // LDS read offset from a lane's base stays an immediate (< 64 KB)
   static constexpr int REDB = 16 * 4 * 256 * ES;            // cross-wave reduction, bytes
   static constexpr int SMEM = 8 * BUFB > REDB ? 8 * BUFB : REDB;
-  static constexpr bool OK = SMEM <= 163840;
+  static constexpr bool OK = SMEM <= 163840 && (P != PREC_BF16X3 || RG % 32 == 0);
 };
 
 template <int P, int STR> struct QuadLanes {
@@ -1384,8 +1384,8 @@ __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
   // address register is spent per k-step
   const int lrow = lane >> 4;
   const int lbase = 2 * rg * G::BUFB;
-  // f32: the element offsets are found before the main loop and the running
-  // sums are loaded during the last chunk; f64 finds and loads them after
+  // f32: the element offsets are found before the main loop and the
+  // running sums are loaded during the last chunk; f64 and split-bf16 find and load them after
   // the loop (held through it they would push the allocation past 128
   // registers into scratch)
   constexpr bool EPF = P == PREC_F32;
@@ -1458,7 +1458,61 @@ __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[f][g][r] = A1(0);
 
+  // split-BF16x3 k-step: 32 rows, K index 8 q + j of lane group q = lane / 16
+  // is row 32 s + 4 j + q (the f32 k-steps 8 s .. 8 s + 7); each product
+  // v = hi + lo with hi = RNE_bf16(v), lo = RNE_bf16(v - hi), and
+  // a b ~ ah bh + ah bl + al bh, accumulated in FP32
+  auto multiply_chunk_bf16 = [&](auto bo_c) __attribute__((always_inline)) {
+    constexpr int BO = decltype(bo_c)::value;
+    if constexpr (P == PREC_BF16X3) {
+#pragma unroll
+    for (int st = 0; st < G::RG / 32; ++st) {
+      bf16x8 Ah[TM], Al[TM], Bh[TN], Bl[TN];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int so = (32 * st + 4 * j) * STR * ES + BO;
+#pragma unroll
+        for (int f = 0; f < TM; ++f) {
+          float v = *(const float*)(smem + ao[f][0] + so);
+#pragma unroll
+          for (int q = 1; q < H; ++q) v *= *(const float*)(smem + ao[f][q] + so);
+          const __bf16 hi = (__bf16)v;
+          Ah[f][j] = hi;
+          Al[f][j] = (__bf16)(v - (float)hi);
+        }
+#pragma unroll
+        for (int g = 0; g < TN; ++g) {
+          float v = 1.0f;
+          if constexpr (MR > 0) {
+            v = *(const float*)(smem + bo[g][0] + so);
+#pragma unroll
+            for (int q = 1; q < MR; ++q) v *= *(const float*)(smem + bo[g][q] + so);
+          }
+          const __bf16 hi = (__bf16)v;
+          Bh[g][j] = hi;
+          Bl[g][j] = (__bf16)(v - (float)hi);
+        }
+        // at most two rows' reads in flight (all eight would not fit in
+        // registers)
+        if (j & 1) __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int f = 0; f < TM; ++f)
+#pragma unroll
+        for (int g = 0; g < TN; ++g) {
+          acc[f][g] = mma16(Al[f], Bh[g], acc[f][g]);
+          acc[f][g] = mma16(Ah[f], Bl[g], acc[f][g]);
+          acc[f][g] = mma16(Ah[f], Bh[g], acc[f][g]);
+        }
+    }
+    }
+  };
+
   auto multiply_chunk = [&](auto bo_c) __attribute__((always_inline)) {
+    if constexpr (P == PREC_BF16X3) {
+      multiply_chunk_bf16(bo_c);
+      return;
+    }
     constexpr int BO = decltype(bo_c)::value;
     constexpr bool PIPE = (P == PREC_F32);
     constexpr int NB = PIPE ? 2 : 1;
@@ -1669,7 +1723,7 @@ hipError_t launch_update_batch(int prec, int str, bool vl, int kmax, const UpdAr
 
 template <int P, int STR, bool VL>
 static void launch_kmax(int kmax, const UpdArgs& a, int nitems, hipStream_t st) {
-  if constexpr (VL && P != PREC_BF16X3 && QuadGeom<P, STR>::OK) {
+  if constexpr (VL && QuadGeom<P, STR>::OK) {
     if (a.quad) {
       // a.items holds nitems rounded up to whole groups of four
       const dim3 grid((unsigned)((nitems + 3) / 4 + (a.with_norms ? 1 : 0)));
@@ -1699,6 +1753,7 @@ bool update_quad_supported(int prec, int n) {
   };
   if (prec == PREC_F32) return ok(IntC<PREC_F32>{});
   if (prec == PREC_F64) return ok(IntC<PREC_F64>{});
+  if (prec == PREC_BF16X3) return ok(IntC<PREC_BF16X3>{});
   return false;
 }
 
