@@ -302,6 +302,16 @@ int64_t cum_plan_coverage(int n, int b, int k, int32_t *hits);
  */
 int64_t cum_plan_items(int n, int d, int b);
 
+/*
+ * cum_plan_groups -- host-only view of how one update launch of the
+ * four-tile kernel packs those tiles into workgroups: returns the number of
+ * workgroups (four tiles each, padded with empty tiles) and, when the arrays
+ * are not NULL, fills per workgroup the 16x16 fragments its tiles multiply
+ * (`frags`) and its real tiles (`tiles`), one int each.  A negative status
+ * on bad arguments.
+ */
+int64_t cum_plan_groups(int n, int d, int b, int32_t *frags, int32_t *tiles);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,7 +35,7 @@ EXPORTS = ("cum_init", "cum_update", "cum_get", "cum_get_moments", "cum_norms",
            "cum_profile_enable", "cum_profile_read", "cum_batch_create", "cum_batch_update",
            "cum_batch_sync", "cum_batch_free", "cum_loss_grad",
            "cum_init_fifo", "cum_set_combine", "cum_recompute", "cum_loss_plan_create",
-           "cum_loss_plan_grad", "cum_loss_plan_free", "cum_profile_sample")
+           "cum_loss_plan_grad", "cum_loss_plan_free", "cum_profile_sample", "cum_plan_groups")
 
 
 class CumError(RuntimeError):
@@ -68,6 +68,7 @@ def _load():
         "cum_last_error": (ctypes.c_char_p, []),
         "cum_plan_coverage": (i64, [i32, i32, i32, ctypes.POINTER(ctypes.c_int32)]),
         "cum_plan_items": (i64, [i32, i32, i32]),
+        "cum_plan_groups": (i64, [i32, i32, i32, ctypes.c_void_p, ctypes.c_void_p]),
         "cum_profile_enable": (i32, [vp, i32]),
         "cum_profile_sample": (i32, [vp, i32]),
         "cum_batch_create": (i32, [ctypes.POINTER(vp), ctypes.POINTER(vp), i32]),
@@ -255,6 +256,17 @@ def cum_plan_coverage(n: int, b: int, k: int):
 
 def cum_plan_items(n: int, d: int, b: int) -> int:
     return int(_lib.cum_plan_items(n, d, b))
+
+
+def cum_plan_groups(n: int, d: int, b: int):
+    """(fragments, tiles) per workgroup of the four-tile update launch (host only)."""
+    ng = int(_lib.cum_plan_groups(n, d, b, None, None))
+    if ng < 0:
+        raise CumError(ng, "cum_plan_groups")
+    frags = np.zeros(ng, np.int32)
+    tiles = np.zeros(ng, np.int32)
+    _lib.cum_plan_groups(n, d, b, frags.ctypes.data, tiles.ctypes.data)
+    return frags, tiles
 
 
 PROFILE_CLASSES = {"update": 1, "combine": 2, "norms": 4}

@@ -405,6 +405,26 @@ int64_t cum_plan_items(int n, int d, int b) {
   return (int64_t)build_items(T, 1, d, 32, 32).size();
 }
 
+int64_t cum_plan_groups(int n, int d, int b, int32_t* frags, int32_t* tiles) {
+  if (check_shape(n, d, b) != CUM_OK) return CUM_EINVAL;
+  Tables T;
+  if (build_tables(n, b, d, T) != 0) return CUM_EINVAL;
+  const std::vector<UpdItem> q = pack_quads(build_items(T, 1, d, 32, 32));
+  const size_t ng = q.size() / 4;
+  for (size_t g = 0; g < ng; ++g) {
+    int32_t f = 0, t = 0;
+    for (size_t j = 0; j < 4; ++j) {
+      const UpdItem& it = q[g * 4 + j];
+      if (it.M == 0) continue;
+      f += (it.M - it.r0 > 16 ? 2 : 1) * (it.N - it.c0 > 16 ? 2 : 1);
+      ++t;
+    }
+    if (frags) frags[g] = f;
+    if (tiles) tiles[g] = t;
+  }
+  return (int64_t)ng;
+}
+
 namespace {
 
 // Shared by cum_init and cum_init_fifo (fifo_p = 0: plain sliding mode).

@@ -95,3 +95,30 @@ def test_dtype_mismatch_is_rejected_by_binding():
         cum.cum_init(5, 3, 1, np.zeros((10, 5), np.float64), prec="fp32")
     with pytest.raises(ValueError):
         cum.cum_init(5, 3, 1, np.zeros((10, 4), np.float32), prec="fp32")
+
+
+def _pivot_dims(n, d, b):
+    nbar = -(-n // b)
+    for k in range(1, d + 1):
+        h = (k + 1) // 2
+        m = k - h
+        for v in range(nbar):
+            rows = math.comb(v + h - 1, h - 1) * b ** h
+            cols = (math.comb(nbar - v + m - 1, m) if m else 1) * b ** m
+            yield rows, cols
+
+
+@pytest.mark.parametrize("n,d,b", [(60, 4, 4), (32, 4, 4), (48, 6, 4), (20, 4, 2), (13, 3, 3)])
+def test_four_tile_packing(n, d, b):
+    """Every 32x32 tile lands in exactly one four-tile workgroup, each
+    multiplies exactly its 16x16 fragments inside the pivot GEMM, and the
+    dearest workgroup stays within one tile (4 fragments) of the average."""
+    import paper_1701_06446_amd as cum
+
+    frags, tiles = cum.cum_plan_groups(n, d, b)
+    items = cum.cum_plan_items(n, d, b)
+    want = sum(-(-r // 16) * -(-c // 16) for r, c in _pivot_dims(n, d, b))
+    assert len(frags) == -(-items // 4)
+    assert tiles.sum() == items and tiles.max() <= 4
+    assert frags.sum() == want
+    assert frags.max() <= -(-want // len(frags)) + 3
