@@ -194,3 +194,39 @@ def test_profile_sampling_counts():
     cum.cum_update(ctx, dev[560:580], dev[160:180])
     assert cum.cum_profile_read(ctx)["update"][0] == 2
     cum.cum_free(ctx)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_norms_carried_by_next_update(prec):
+    """A step's norms are finished by the next update launch (one extra
+    workgroup) or on demand: after two updates the device buffer holds the
+    first update's norms as that launch formed them, and cum_norms then
+    forms and returns the second's; both against the oracle."""
+    import ctypes
+
+    import torch
+
+    import paper_1701_06446_amd as cum
+
+    n, d, b, t, p = 24, 4, 4, 600, 50
+    rows = as_input(_rows(11, t + 2 * p, n), prec)
+    dev = to_device(rows)
+    ctx = cum.cum_init(n, d, b, dev[:t], prec=prec)
+    ptr = cum.cum_norms_device(ctx)  # the buffer's address does not change
+    orc = oracle.SlidingOracle(rows[:t], n, d, b)
+    cum.cum_update(ctx, dev[t:t + p], dev[:p])
+    orc.update(rows[t:t + p], rows[:p])
+    fo1, _ = oracle.norms(orc.cumulants(), n, b)
+    cum.cum_update(ctx, dev[t + p:t + 2 * p], dev[p:2 * p])
+    orc.update(rows[t + p:t + 2 * p], rows[p:2 * p])
+    fo2, _ = oracle.norms(orc.cumulants(), n, b)
+    torch.cuda.synchronize()
+    host = np.zeros(2 * (d + 1), np.float64)
+    hip = ctypes.CDLL("libamdhip64.so")
+    assert hip.hipMemcpy(ctypes.c_void_p(host.ctypes.data), ctypes.c_void_p(ptr),
+                         ctypes.c_size_t(host.nbytes), 2) == 0  # device to host
+    tol = max(TOL[prec], 1e-12)
+    np.testing.assert_allclose(host[1:d + 1], fo1[1:], rtol=tol)
+    fro, nu = cum.cum_norms(ctx)
+    np.testing.assert_allclose(fro[1:], fo2[1:], rtol=tol)
+    cum.cum_free(ctx)
