@@ -350,7 +350,7 @@ __device__ void upd_body(const UpdArgs& a, const UpdItem& it, char* smem) {
     // f32: the factor values of k-step s+1 are loaded while k-step s
     // multiplies (f64 loads them just before use: two buffers of doubles
     // would cost the fourth wave per SIMD)
-    constexpr bool PIPE = (P == PREC_F32);
+    constexpr bool PIPE = (P == PREC_F32 || P == PREC_F64);
     constexpr int NB = PIPE ? 2 : 1;
     T fa[NB][TM][H], fb[NB][TN][MRC];
     auto load_factors = [&](int st, int buf) __attribute__((always_inline)) {
@@ -1514,7 +1514,7 @@ __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
       return;
     }
     constexpr int BO = decltype(bo_c)::value;
-    constexpr bool PIPE = (P == PREC_F32);
+    constexpr bool PIPE = (P == PREC_F32 || P == PREC_F64);
     constexpr int NB = PIPE ? 2 : 1;
     T fa[NB][TM][H], fb[NB][TN][MRC];
     auto load_factors = [&](int st, int buf) __attribute__((always_inline)) {
