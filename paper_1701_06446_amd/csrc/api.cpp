@@ -780,7 +780,8 @@ struct cum_batch {
   bool own_stream = false;
   std::vector<UpdArgs> h_upd;
   UpdArgs* d_upd = nullptr;
-  struct Group { int str; bool vl; int kmax; UpdItem* items; int nitems; int grid; };
+  // quad: four-tile workgroups (items in groups of four tiles of one member)
+  struct Group { int str; bool vl; int kmax; UpdItem* items; int nitems; int grid; bool quad; };
   std::vector<Group> groups;
   CombArgs* d_comb[CUM_MAXD + 1] = {};
   int64_t* comb_items[CUM_MAXD + 1] = {};
@@ -826,7 +827,10 @@ hipError_t bupload(cum_batch* bt, V** dst, const V* src, size_t count) {
 
 int batch_launch_all(cum_batch* bt) {
   for (const auto& g : bt->groups)
-    CUM_TRY(launch_update_batch(bt->prec, g.str, g.vl, g.kmax, bt->d_upd, g.items, g.nitems, g.grid, bt->stream));
+    if (g.quad)
+      CUM_TRY(launch_update_quad_batch(bt->prec, g.str, g.kmax, bt->d_upd, g.items, g.nitems, g.grid, bt->stream));
+    else
+      CUM_TRY(launch_update_batch(bt->prec, g.str, g.vl, g.kmax, bt->d_upd, g.items, g.nitems, g.grid, bt->stream));
   for (int s = 1; s <= CUM_MAXD; ++s)
     CUM_TRY(launch_combine_lattice_batch(bt->prec, s, bt->d_lat, bt->lat_items[s], bt->nlat[s], bt->lat_grid[s],
                                          bt->lat_lds[s], bt->stream));
@@ -896,19 +900,21 @@ int cum_batch_create(cum_batch** out, cum_ctx* const* ctxs, int m) {
   for (const auto& k : keys) {
     std::vector<UpdItem> items;
     int kmax = 1;
+    const bool quad = k.vl && update_quad_batch_supported(bt->prec, k.str);
     for (int i : order) {
       cum_ctx* c = ctxs[i];
       if (c->stride != k.str || ((c->n * (int)c->x_size) % 16 == 0) != k.vl) continue;
       if (c->tm != 2 || c->tn != 2) return fail(CUM_EINVAL);
       kmax = std::max(kmax, c->d);
       std::vector<UpdItem> ci = build_items(c->T, 1, c->d, 32, 32);
+      if (quad) ci = pack_quads(ci);  // padding tiles keep the member's index
       for (auto& it : ci) {
         it.ctx = i;
         items.push_back(it);
       }
     }
-    cum_batch::Group g{k.str, k.vl, kmax, nullptr, (int)items.size(), 0};
-    g.grid = std::min(g.nitems, pgrid);
+    cum_batch::Group g{k.str, k.vl, kmax, nullptr, (int)items.size(), 0, quad};
+    g.grid = quad ? std::min(g.nitems / 4, ncu) : std::min(g.nitems, pgrid);
     if (bupload(bt, &g.items, items.data(), items.size()) != hipSuccess) return fail(CUM_ENOMEM);
     bt->groups.push_back(g);
   }

@@ -110,6 +110,12 @@ hipError_t launch_combine_lattice_batch(int prec, int d, const LatArgs* ctxs, co
 // Batched launches over several contexts (device-resident argument tables).
 hipError_t launch_update_batch(int prec, int str, bool vl, int kmax, const UpdArgs* ctxs, const UpdItem* items,
                                int nitems, int grid, hipStream_t st);
+// Batched four-tile form: items holds groups of four tiles of one member
+// each (pack_quads per member), nitems a multiple of 4; grid workgroups walk
+// the groups with a grid-sized stride.
+bool update_quad_batch_supported(int prec, int str);
+hipError_t launch_update_quad_batch(int prec, int str, int kmax, const UpdArgs* ctxs, const UpdItem* items,
+                                    int nitems, int grid, hipStream_t st);
 hipError_t launch_combine_batch(int prec, int s, const CombArgs* ctxs, const int64_t* items, int nitems,
                                 int grid, size_t stage_bytes, hipStream_t st);
 hipError_t launch_norms_batch(const NormArgs* ctxs, int m, hipStream_t st);

@@ -347,9 +347,7 @@ __device__ void upd_body(const UpdArgs& a, const UpdItem& it, char* smem) {
   // k-steps of one chunk held at byte offset BO of smem (f32/f64 paths)
   auto multiply_chunk = [&](auto bo_c) __attribute__((always_inline)) {
     constexpr int BO = decltype(bo_c)::value;
-    // f32: the factor values of k-step s+1 are loaded while k-step s
-    // multiplies (f64 loads them just before use: two buffers of doubles
-    // would cost the fourth wave per SIMD)
+    // the factor values of k-step s+1 are loaded while k-step s multiplies
     constexpr bool PIPE = (P == PREC_F32 || P == PREC_F64);
     constexpr int NB = PIPE ? 2 : 1;
     T fa[NB][TM][H], fb[NB][TN][MRC];
@@ -1659,6 +1657,30 @@ __device__ __forceinline__ void upd_quad_shape(const UpdArgs& a, const UpdItem& 
 // Each tile's waves take the body of its order and shape; every body runs
 // the same chunk loop (same barriers), so the tiles of one workgroup may
 // differ in both.
+// Batched form: every workgroup walks groups of four tiles of one member
+// (its arguments from ctxs[]); all tiles of a group share the member's rows,
+// so its waves pass the same barriers.
+template <int P, int STR, int KMAX>
+__global__ __launch_bounds__(1024) void k_update_quad_batch(const UpdArgs* __restrict__ ctxs,
+                                                            const UpdItem* __restrict__ items, int ngroups) {
+  __shared__ __attribute__((aligned(16))) char smem[QuadGeom<P, STR>::SMEM];
+  const int tile = __builtin_amdgcn_readfirstlane(threadIdx.x >> 8);
+  for (int q = blockIdx.x; q < ngroups; q += gridDim.x) {
+    const UpdItem it = items[q * 4 + tile];
+    const UpdArgs& a = ctxs[it.ctx];
+    switch (it.k) {
+      case 1: upd_quad_shape<P, 1, 0, STR>(a, it, smem); break;
+      case 2: upd_quad_shape<P, 1, 1, STR>(a, it, smem); break;
+      case 3: upd_quad_shape<P, 2, 1, STR>(a, it, smem); break;
+      case 4: upd_quad_shape<P, 2, 2, STR>(a, it, smem); break;
+      case 5: if constexpr (KMAX >= 5) upd_quad_shape<P, 3, 2, STR>(a, it, smem); break;
+      case 6: if constexpr (KMAX >= 6) upd_quad_shape<P, 3, 3, STR>(a, it, smem); break;
+      default: break;
+    }
+    __syncthreads();  // the next group's chunk 0 lands on the reduction buffer
+  }
+}
+
 template <int P, int STR, int KMAX>
 __global__ __launch_bounds__(1024) void k_update_quad(UpdArgs a) {
   __shared__ __attribute__((aligned(16))) char smem[QuadGeom<P, STR>::SMEM];
@@ -1706,6 +1728,62 @@ static hipError_t launch_batch_p(int str, bool vl, int kmax, const UpdArgs* ctxs
                         : launch_batch_one<P, 132, false>(kmax, ctxs, items, nitems, grid, st);
     case 260: return vl ? launch_batch_one<P, 260, true>(kmax, ctxs, items, nitems, grid, st)
                         : launch_batch_one<P, 260, false>(kmax, ctxs, items, nitems, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int P, int STR>
+static hipError_t launch_quad_batch_s(int kmax, const UpdArgs* ctxs, const UpdItem* items, int nitems, int grid,
+                                      hipStream_t st) {
+  if constexpr (QuadGeom<P, STR>::OK) {
+    if (nitems % 4) return hipErrorInvalidValue;
+    if (kmax <= 4)
+      hipLaunchKernelGGL((k_update_quad_batch<P, STR, 4>), dim3(grid), dim3(1024), 0, st, ctxs, items, nitems / 4);
+    else
+      hipLaunchKernelGGL((k_update_quad_batch<P, STR, 6>), dim3(grid), dim3(1024), 0, st, ctxs, items, nitems / 4);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int P>
+static hipError_t launch_quad_batch_p(int str, int kmax, const UpdArgs* ctxs, const UpdItem* items, int nitems,
+                                      int grid, hipStream_t st) {
+  switch (str) {
+    case 36: return launch_quad_batch_s<P, 36>(kmax, ctxs, items, nitems, grid, st);
+    case 68: return launch_quad_batch_s<P, 68>(kmax, ctxs, items, nitems, grid, st);
+    case 132: return launch_quad_batch_s<P, 132>(kmax, ctxs, items, nitems, grid, st);
+    case 260: return launch_quad_batch_s<P, 260>(kmax, ctxs, items, nitems, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+bool update_quad_batch_supported(int prec, int str) {
+  auto ok = [&](auto p) {
+    constexpr int PP = decltype(p)::value;
+    switch (str) {
+      case 36: return QuadGeom<PP, 36>::OK;
+      case 68: return QuadGeom<PP, 68>::OK;
+      case 132: return QuadGeom<PP, 132>::OK;
+      case 260: return QuadGeom<PP, 260>::OK;
+      default: return false;
+    }
+  };
+  if (prec == PREC_F32) return ok(IntC<PREC_F32>{});
+  if (prec == PREC_F64) return ok(IntC<PREC_F64>{});
+  if (prec == PREC_BF16X3) return ok(IntC<PREC_BF16X3>{});
+  return false;
+}
+
+hipError_t launch_update_quad_batch(int prec, int str, int kmax, const UpdArgs* ctxs, const UpdItem* items,
+                                    int nitems, int grid, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  if (kmax < 1 || kmax > 6) return hipErrorInvalidValue;
+  switch (prec) {
+    case PREC_F64: return launch_quad_batch_p<PREC_F64>(str, kmax, ctxs, items, nitems, grid, st);
+    case PREC_F32: return launch_quad_batch_p<PREC_F32>(str, kmax, ctxs, items, nitems, grid, st);
+    case PREC_BF16X3: return launch_quad_batch_p<PREC_BF16X3>(str, kmax, ctxs, items, nitems, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
