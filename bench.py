@@ -38,8 +38,8 @@ TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 1e-4}
 # each scaled by the ratio of known bytes to the same counter on a plain
 # device copy.  Valid only for the kernel source they were taken on.
 TRAFFIC = {"prec": "fp32",
-           "kernels_sha256": "c4b0802ee92b1ccf19e0aa3cf73aa30a9329119664f0147ec41e731ad402b598",
-           "fetch_bytes": 6096.06 * 1024 * 1.99988,   # FETCH_SIZE KiB x (256 MiB / 131078.5 KiB)
+           "kernels_sha256": "2f11412f710bb2cfd1325968bf0d5c17c9c56e7c66e24a6e172bffb96bb6c4ba",
+           "fetch_bytes": 6095.99 * 1024 * 1.99988,   # FETCH_SIZE KiB x (256 MiB / 131078.5 KiB)
            "write_bytes": 6476.03 * 1024 * 1.00000}   # WRITE_SIZE KiB x (256 MiB / 262144.0 KiB)
 
 
