@@ -63,7 +63,7 @@ def candidates(n: int, prec: str):
     return [b for b in CANDIDATES if b <= n] or [1]
 
 
-def time_update(n, d, b, t, p, prec, reps=4, seed=0) -> float:
+def time_update(n, d, b, t, p, prec, reps=12, seed=0) -> float:
     """Mean update time (ms) of one context of this shape on the device."""
     import torch
 
