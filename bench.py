@@ -376,7 +376,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the order-6 and adjoint legs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
