@@ -99,3 +99,42 @@ def test_batch_rejects_host_pointers():
                              [h[:s.p] for s, h in zip(ss, hosts)])
     assert e.value.status == cum.CUM_EINVAL
     cum.cum_batch_free(bt)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_with_an_idle_member(prec):
+    """A member handed 0 rows in a batch step keeps its state (its tiles run
+    with no chunks); the others slide as usual."""
+    import paper_1701_06446_amd as cum
+
+    ss = streams.batched_streams(m=3, steps=3, workload_id=12, n_max=32)
+    dev = [to_device(as_input(s.rows, prec)) for s in ss]
+    ctxs = [cum.cum_init(s.n, s.d, s.b, d[:s.t], prec=prec) for s, d in zip(ss, dev)]
+    ref = [cum.cum_init(s.n, s.d, s.b, d[:s.t], prec=prec) for s, d in zip(ss, dev)]
+    bt = cum.cum_batch_create(ctxs)
+    done = [0, 0, 0]
+    for w in range(1, 4):
+        xn, xo = [], []
+        for i, (s, d) in enumerate(zip(ss, dev)):
+            if w == 2 and i == 1:
+                xn.append(d[:0])
+                xo.append(d[:0])
+                continue
+            done[i] += 1
+            c = done[i]
+            xn.append(d[s.t + (c - 1) * s.p:s.t + c * s.p])
+            xo.append(d[(c - 1) * s.p:c * s.p])
+        cum.cum_batch_update(bt, xn, xo)
+        for r, a, b in zip(ref, xn, xo):
+            if a.shape[0]:
+                cum.cum_update(r, a, b)
+    cum.cum_batch_sync(bt)
+    for c, r, s in zip(ctxs, ref, ss):
+        for k in range(1, s.d + 1):
+            assert_same_to_rounding(cum.cum_get(c, k), cum.cum_get(r, k), prec, k, s.n, s.b, k)
+        fc, _ = cum.cum_norms(c)
+        fr, _ = cum.cum_norms(r)
+        assert_same_to_rounding(fc[1:], fr[1:], prec, "norms")
+    cum.cum_batch_free(bt)
+    for c in ctxs + ref:
+        cum.cum_free(c)
