@@ -791,10 +791,11 @@ struct cum_batch {
   NormArgs* d_norm = nullptr;
   // fused combine of the members whose lattices fit, one launch per order d
   LatArgs* d_lat = nullptr;
-  int64_t* lat_items[CUM_MAXD + 1] = {};
-  int nlat[CUM_MAXD + 1] = {};
-  int lat_grid[CUM_MAXD + 1] = {};
-  size_t lat_lds[CUM_MAXD + 1] = {};
+  // fused-combine launches, one per (order d, lattice size): a launch's
+  // workgroups all reserve its largest lattice, so members of small b do not
+  // share the LDS reservation (and occupancy) of a b = 8 member
+  struct LatGroup { int d; int64_t* items; int n; int grid; size_t lds; };
+  std::vector<LatGroup> lat_groups;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipEvent_t done = nullptr;
@@ -831,9 +832,8 @@ int batch_launch_all(cum_batch* bt) {
       CUM_TRY(launch_update_quad_batch(bt->prec, g.str, g.kmax, bt->d_upd, g.items, g.nitems, g.grid, bt->stream));
     else
       CUM_TRY(launch_update_batch(bt->prec, g.str, g.vl, g.kmax, bt->d_upd, g.items, g.nitems, g.grid, bt->stream));
-  for (int s = 1; s <= CUM_MAXD; ++s)
-    CUM_TRY(launch_combine_lattice_batch(bt->prec, s, bt->d_lat, bt->lat_items[s], bt->nlat[s], bt->lat_grid[s],
-                                         bt->lat_lds[s], bt->stream));
+  for (const auto& g : bt->lat_groups)
+    CUM_TRY(launch_combine_lattice_batch(bt->prec, g.d, bt->d_lat, g.items, g.n, g.grid, g.lds, bt->stream));
   for (int s = 1; s <= CUM_MAXD; ++s)
     CUM_TRY(launch_combine_batch(bt->prec, s, bt->d_comb[s], bt->comb_items[s], bt->ncomb[s], bt->comb_grid[s],
                                  bt->stage_bytes[s], bt->stream));
@@ -926,19 +926,23 @@ int cum_batch_create(cum_batch** out, cum_ctx* const* ctxs, int m) {
       if (ctxs[i]->lat_lds > 0) la[(size_t)i] = lat_args(ctxs[i]);
     if (bupload(bt, &bt->d_lat, la.data(), la.size()) != hipSuccess) return fail(CUM_ENOMEM);
     for (int dd = 1; dd <= CUM_MAXD; ++dd) {
-      std::vector<int64_t> items;
-      size_t lds = 16;
-      for (int i : order) {
-        cum_ctx* c = ctxs[i];
-        if (c->lat_lds == 0 || c->d != dd) continue;
-        for (int64_t blk = 0; blk < c->T.ord[dd].nblocks; ++blk) items.push_back(((int64_t)i << 40) | blk);
-        lds = std::max(lds, c->lat_lds);
+      std::vector<size_t> sizes;
+      for (int i : order)
+        if (ctxs[i]->lat_lds > 0 && ctxs[i]->d == dd &&
+            std::find(sizes.begin(), sizes.end(), ctxs[i]->lat_lds) == sizes.end())
+          sizes.push_back(ctxs[i]->lat_lds);
+      for (size_t lds : sizes) {
+        std::vector<int64_t> items;
+        for (int i : order) {
+          cum_ctx* c = ctxs[i];
+          if (c->lat_lds != lds || c->d != dd) continue;
+          for (int64_t blk = 0; blk < c->T.ord[dd].nblocks; ++blk) items.push_back(((int64_t)i << 40) | blk);
+        }
+        cum_batch::LatGroup g{dd, nullptr, (int)items.size(), 0, lds};
+        g.grid = std::min(g.n, ncu * 24);
+        if (bupload(bt, &g.items, items.data(), items.size()) != hipSuccess) return fail(CUM_ENOMEM);
+        bt->lat_groups.push_back(g);
       }
-      if (items.empty()) continue;
-      bt->nlat[dd] = (int)items.size();
-      bt->lat_grid[dd] = std::min(bt->nlat[dd], ncu * 24);
-      bt->lat_lds[dd] = lds;
-      if (bupload(bt, &bt->lat_items[dd], items.data(), items.size()) != hipSuccess) return fail(CUM_ENOMEM);
     }
   }
   // per-order combine of the other members: one entry per context (unused
