@@ -171,7 +171,9 @@ int cum_norms_device(cum_ctx *ctx, const double **dev_ptr);
  * cum_profile_enable -- `on` is a mask of kernel classes (bit 0 = moment
  * update, bit 1 = cumulant combine, bit 2 = norms; 0 switches profiling
  * off): every launch of a selected class is bracketed by HIP events on the
- * context's stream (each pair adds a short gap between launches).
+ * context's stream (each pair adds a short gap between launches).  The
+ * norms' reduction usually rides on the next update launch and is timed
+ * with it; class 2 sees only its launches on its own (cum_sync & co.).
  * Synchronises and clears earlier records.
  */
 int cum_profile_enable(cum_ctx *ctx, int on);
