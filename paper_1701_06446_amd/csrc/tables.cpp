@@ -8,6 +8,8 @@
 #include "tables.h"
 
 #include <algorithm>
+#include <functional>
+#include <queue>
 #include <unordered_map>
 
 namespace cum {
@@ -203,13 +205,18 @@ std::vector<UpdItem> pack_quads(const std::vector<UpdItem>& items) {
   empty.N = 0;
   for (size_t g = 0; g < ng; ++g)
     for (int j = 0; j < 4; ++j) out[g * 4 + (size_t)j] = empty;
+  // open groups in a min-heap of (cost so far, index): the least loaded,
+  // lowest index first
+  using Slot = std::pair<int, size_t>;
+  std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> open;
+  for (size_t g = 0; g < ng; ++g) open.push({0, g});
   for (size_t i : order) {
-    size_t best = ng;
-    for (size_t g = 0; g < ng; ++g)
-      if (fill[g] < 4 && (best == ng || load[g] < load[best])) best = g;
+    const size_t best = open.top().second;
+    open.pop();
     out[best * 4 + (size_t)fill[best]] = items[i];
     ++fill[best];
     load[best] += cost(items[i]);
+    if (fill[best] < 4) open.push({load[best], best});
   }
   return out;
 }
