@@ -171,7 +171,7 @@ def run_path(path, s, warmup, steps, check, host_leg=False):
             cum.cum_update(ctx, rows[T + lo:T + hi], None if mode == "fifo" else rows[lo:hi])
         torch.cuda.synchronize()
         out["host_input_rows_per_s"] = 20 * P / (time.perf_counter() - t3)
-    # the recalculation the update replaces (Eq. (upcmplx), Sec. 3.3): the whole
+    # the recalculation the update replaces (Eq. (upcmplx), Sec. 2.4): the whole
     # current window contracted from scratch on the same context, with the
     # combine and norms; the paper's speed-up estimate is t / (2 t_up + B(d))
     win = dev[w * P: w * P + T]

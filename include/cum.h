@@ -109,8 +109,9 @@ int cum_update(cum_ctx *ctx, const void *X_new, const void *X_old, int64_t p);
  * cum_recompute -- recalculate the context's moments from scratch over the
  * window X (t x n rows, the t of cum_init, host or device, same element type
  * as cum_init's), then its cumulants and norms: the recalculation that
- * Eq. (upcmplx) and Sec. 3.3 compare the update with.  The running sums are
- * zeroed first, so any rounding accumulated by earlier updates is dropped;
+ * Eq. (upcmplx) (Sec. 2.4) and Eq. (complxn) (Sec. 2.6) compare the update
+ * with.  The running sums are zeroed first, so any rounding accumulated by
+ * earlier updates is dropped;
  * a FIFO context (cum_init_fifo) refills its t/p batch slots from X's
  * batches, oldest first.  Asynchronous on the context's stream for device X;
  * host X is staged and the call synchronises.
@@ -119,7 +120,7 @@ int cum_recompute(cum_ctx *ctx, const void *X);
 
 /*
  * cum_init_fifo -- like cum_init, but the context keeps the FIFO of batch
- * moments that Sec. 3.1 describes as the alternative to contracting the rows
+ * moments that Sec. 2.4 describes (after Alg. 2) as the alternative to contracting the rows
  * that leave the window: the window is cut into t/p batches of p rows
  * (oldest first), and the increment sum_{batch} x^(k) of every batch is kept
  * per stored element (t/p slots per order: FP64 on the CUM_FP64 path, else

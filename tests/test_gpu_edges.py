@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.gpu_helpers import TOL, as_input, rel_err, to_device
+from tests.gpu_helpers import TOL, as_input, assert_mean_match, assert_norms_match, rel_err, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -28,13 +28,16 @@ def _check_against_oracle(n, d, b, t, p, steps, prec, seed=0, device=True, data=
         cum.cum_update(ctx, src[t + (w - 1) * p:t + w * p], src[(w - 1) * p:w * p])
         orc.update(rows[t + (w - 1) * p:t + w * p], rows[(w - 1) * p:w * p])
     Co = orc.cumulants()
-    errs = [rel_err(cum.cum_get(ctx, k), Co[k - 1], n, b, k) for k in range(1, d + 1)]
+    Cg = [cum.cum_get(ctx, k) for k in range(1, d + 1)]
+    errs = [rel_err(Cg[k - 1], Co[k - 1], n, b, k) for k in range(1, d + 1)]
     fro, nu = cum.cum_norms(ctx)
     cum.cum_free(ctx)
     gate = errs[1:] if d > 1 else errs
     assert max(gate) <= TOL[prec], (n, d, b, t, p, prec, errs)
+    if d > 1:
+        assert_mean_match(Cg[0], Co[0], Co[1], n, b, prec)
     fo, no = oracle.norms(Co, n, b)
-    np.testing.assert_allclose(fro[1:], fo[1:], rtol=max(TOL[prec], 1e-12))
+    assert_norms_match(fro, nu, fo, no, prec)
     return errs, fro, nu
 
 

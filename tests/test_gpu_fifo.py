@@ -1,4 +1,4 @@
-"""FIFO mode (the batch-moment queue of Sec. 3.1): the window's moments are
+"""FIFO mode (the batch-moment queue of Sec. 2.4, after Alg. 2): the window's moments are
 the same numbers as in sliding mode, so the checks are the oracle on the
 current window, past the point where the queue has wrapped around (every
 stored increment replaced at least once); bit-exact sums on integer-valued

@@ -4,7 +4,7 @@ import pytest
 
 import oracle
 import streams
-from tests.gpu_helpers import TOL, as_input, rel_err, to_device
+from tests.gpu_helpers import TOL, as_input, assert_mean_match, assert_norms_match, rel_err, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -27,12 +27,13 @@ def _run_case(stream, prec, steps, device_inputs=True, check_every=1):
         if w % check_every and w != steps:
             continue
         Co = orc.cumulants()
+        Cg = [cum.cum_get(ctx, k) for k in range(1, d + 1)]
         for k in range(1, d + 1):
-            e = rel_err(cum.cum_get(ctx, k), Co[k - 1], n, b, k)
-            worst[k] = max(worst[k], e)
+            worst[k] = max(worst[k], rel_err(Cg[k - 1], Co[k - 1], n, b, k))
+        assert_mean_match(Cg[0], Co[0], Co[1], n, b, prec)
         fro_g, nu_g = cum.cum_norms(ctx)
         fro_o, nu_o = oracle.norms(Co, n, b)
-        np.testing.assert_allclose(fro_g[1:], fro_o[1:], rtol=max(TOL[prec], 1e-12))
+        assert_norms_match(fro_g, nu_g, fro_o, nu_o, prec)
     cum.cum_free(ctx)
     print("prec=%s worst rel err per order: %s" % (prec, worst[1:]))
     assert np.all(worst[2:] <= TOL[prec]), worst
