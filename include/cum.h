@@ -106,6 +106,23 @@ int cum_init(cum_ctx **ctx, int n, int d, int b, const void *X, int64_t t, int p
 int cum_update(cum_ctx *ctx, const void *X_new, const void *X_old, int64_t p);
 
 /*
+ * cum_update_noalloc -- cum_update for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, semantics and errors as cum_update,
+ * but host inputs are staged through a fixed device array of the library
+ * (16 MiB per GPU, held from the first call on that GPU until the process
+ * ends) instead of a buffer allocated on demand: the call allocates nothing
+ * (no hipMalloc / hipFree; profiling events are not recorded during it).
+ *   - CUM_ESIZE, before any work, when the staged rows exceed the array:
+ *     p * n * sizeof(element) * (2, or 1 on a FIFO context) > 16 MiB.
+ *   - CUM_EINVAL when the current device is not the one cum_init ran on.
+ *   - Synchronises the context's stream before returning, so the array is
+ *     free again.  Every call on one GPU shares that GPU's array: calls that
+ *     overlap on one GPU (from several threads) race.
+ */
+int cum_update_noalloc(cum_ctx *ctx, const void *X_new, const void *X_old, int64_t p);
+
+/*
  * cum_recompute -- recalculate the context's moments from scratch over the
  * window X (t x n rows, the t of cum_init, host or device, same element type
  * as cum_init's), then its cumulants and norms: the recalculation that

@@ -35,7 +35,8 @@ EXPORTS = ("cum_init", "cum_update", "cum_get", "cum_get_moments", "cum_norms",
            "cum_profile_enable", "cum_profile_read", "cum_batch_create", "cum_batch_update",
            "cum_batch_sync", "cum_batch_free", "cum_loss_grad",
            "cum_init_fifo", "cum_set_combine", "cum_recompute", "cum_loss_plan_create",
-           "cum_loss_plan_grad", "cum_loss_plan_free", "cum_profile_sample", "cum_plan_groups")
+           "cum_loss_plan_grad", "cum_loss_plan_free", "cum_profile_sample", "cum_plan_groups",
+           "cum_update_noalloc")
 
 
 class CumError(RuntimeError):
@@ -56,6 +57,7 @@ def _load():
     sig = {
         "cum_init": (i32, [ctypes.POINTER(vp), i32, i32, i32, vp, i64, i32, vp]),
         "cum_update": (i32, [vp, vp, vp, i64]),
+        "cum_update_noalloc": (i32, [vp, vp, vp, i64]),
         "cum_get": (i32, [vp, i32, vp, sz]),
         "cum_get_moments": (i32, [vp, i32, vp, sz]),
         "cum_norms": (i32, [vp, pd, pd]),
@@ -194,6 +196,19 @@ def cum_update(ctx: Context, X_new, X_old=None):
         if pn != po:
             raise ValueError("X_new and X_old must have the same number of rows")
     _check(_lib.cum_update(ctx.handle, an, ao, pn), "cum_update")
+
+
+def cum_update_noalloc(ctx: Context, X_new, X_old=None):
+    """cum_update that allocates nothing: host inputs are staged through the
+    library's fixed 16 MiB device array; synchronises before returning."""
+    an, pn, _k1 = _pointer(X_new, ctx.prec, ctx.n)
+    if X_old is None:
+        ao = None
+    else:
+        ao, po, _k2 = _pointer(X_old, ctx.prec, ctx.n)
+        if pn != po:
+            raise ValueError("X_new and X_old must have the same number of rows")
+    _check(_lib.cum_update_noalloc(ctx.handle, an, ao, pn), "cum_update_noalloc")
 
 
 def cum_num_blocks(n: int, b: int, k: int) -> int:

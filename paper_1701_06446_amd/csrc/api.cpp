@@ -18,6 +18,7 @@
 #include "../../include/cum.h"
 #include "adjoint.h"
 #include "kernels.h"
+#include "noalloc.h"
 #include "tables.h"
 
 using namespace cum;
@@ -31,6 +32,7 @@ constexpr int64_t kRowChunk = 2048;  // rows per contraction before each compens
 struct cum_ctx {
   int n = 0, d = 0, b = 0, prec = 0;
   int64_t t = 0;
+  int device = 0;        // device current at cum_init
   hipStream_t stream = nullptr;
   bool ready = false;
   Tables T;
@@ -79,6 +81,7 @@ struct cum_ctx {
   bool norms_pending = false;
   NormArgs pending_na{};
   int profile_mask = 0;
+  bool no_events = false;             // set during cum_update_noalloc: no profiling events
   int profile_every = 1;              // bracket one launch in this many per class
   int64_t profile_seen[3] = {0, 0, 0};
   struct Ev { int cls; hipEvent_t a, b; };
@@ -191,7 +194,7 @@ struct Timed {
   int cls;
   hipEvent_t a = nullptr, b = nullptr;
   Timed(cum_ctx* ctx, int k) : c(ctx), cls(k) {
-    if (!(c->profile_mask & (1 << cls))) return;
+    if (!(c->profile_mask & (1 << cls)) || c->no_events) return;
     if (c->profile_seen[cls]++ % c->profile_every != 0) return;
     a = pooled_event(c);
     b = pooled_event(c);
@@ -447,6 +450,11 @@ int init_ctx(cum_ctx** out, int n, int d, int b, const void* X, int64_t t, int64
   c->stream = (hipStream_t)hip_stream;
   c->x_size = (prec == CUM_FP64) ? 8 : 4;
   c->st_size = (prec == CUM_FP64) ? 8 : 4;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return CUM_EDEVICE;
+  }
   if (build_tables(n, b, d, c->T) != 0) { delete c; return CUM_EINVAL; }
   c->stride = update_lds_stride(n);
   c->chunk = c->stride ? update_chunk_rows(prec, c->stride) : 0;
@@ -567,29 +575,31 @@ int cum_init_fifo(cum_ctx** out, int n, int d, int b, const void* X, int64_t t, 
   return init_ctx(out, n, d, b, X, t, p, prec, hip_stream);
 }
 
-int cum_update(cum_ctx* c, const void* X_new, const void* X_old, int64_t p) {
-  if (!c) return CUM_EINVAL;
-  if (!c->ready) return CUM_ESTATE;
-  if (p < 0 || p > c->t) return CUM_EINVAL;
-  if (p == 0) return CUM_OK;
+}  // extern "C"
+
+namespace {
+
+// Shared by cum_update and cum_update_noalloc.  `stage`: where host inputs
+// are copied (nullptr: the context's own buffer, grown on demand).
+int update_impl(cum_ctx* c, const void* X_new, const void* X_old, int64_t p, char* stage) {
   const bool fifo = c->fifo_q > 0;
-  if (fifo && p != c->fifo_p) return CUM_EINVAL;
-  if (!X_new || (!fifo && !X_old)) return CUM_EINVAL;
   const char* xn = (const char*)X_new;
   const char* xo = fifo ? nullptr : (const char*)X_old;
   const size_t bytes = (size_t)p * c->n * c->x_size;
   const bool dn = is_device_ptr(X_new), dob = fifo || is_device_ptr(X_old);
   if (!dn || !dob) {
-    int rc = ensure_stage(c, 2 * bytes);
-    if (rc != CUM_OK) return rc;
-    char* st = (char*)c->stage;
+    if (!stage) {
+      int rc = ensure_stage(c, 2 * bytes);
+      if (rc != CUM_OK) return rc;
+      stage = (char*)c->stage;
+    }
     if (!dn) {
-      CUM_TRY(hipMemcpyAsync(st, X_new, bytes, hipMemcpyHostToDevice, c->stream));
-      xn = st;
+      CUM_TRY(hipMemcpyAsync(stage, X_new, bytes, hipMemcpyHostToDevice, c->stream));
+      xn = stage;
     }
     if (!dob) {
-      CUM_TRY(hipMemcpyAsync(st + bytes, X_old, bytes, hipMemcpyHostToDevice, c->stream));
-      xo = st + bytes;
+      CUM_TRY(hipMemcpyAsync(stage + bytes, X_old, bytes, hipMemcpyHostToDevice, c->stream));
+      xo = stage + bytes;
     }
     // host buffers are free for reuse once this returns
     CUM_TRY(hipStreamSynchronize(c->stream));
@@ -608,6 +618,45 @@ int cum_update(cum_ctx* c, const void* X_new, const void* X_old, int64_t p) {
     if (rc != CUM_OK) return rc;
   }
   return run_combine_and_norms(c);
+}
+
+int check_update_args(cum_ctx* c, const void* X_new, const void* X_old, int64_t p) {
+  if (!c) return CUM_EINVAL;
+  if (!c->ready) return CUM_ESTATE;
+  if (p < 0 || p > c->t) return CUM_EINVAL;
+  const bool fifo = c->fifo_q > 0;
+  if (p > 0 && fifo && p != c->fifo_p) return CUM_EINVAL;
+  if (p > 0 && (!X_new || (!fifo && !X_old))) return CUM_EINVAL;
+  return CUM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cum_update(cum_ctx* c, const void* X_new, const void* X_old, int64_t p) {
+  if (int rc = check_update_args(c, X_new, X_old, p)) return rc;
+  if (p == 0) return CUM_OK;
+  return update_impl(c, X_new, X_old, p, nullptr);
+}
+
+int cum_update_noalloc(cum_ctx* c, const void* X_new, const void* X_old, int64_t p) {
+  if (int rc = check_update_args(c, X_new, X_old, p)) return rc;
+  if (p == 0) return CUM_OK;
+  const int nin = c->fifo_q > 0 ? 1 : 2;
+  if ((size_t)nin * (size_t)p * c->n * c->x_size > NOALLOC_STAGE_BYTES) return CUM_ESIZE;
+  int dev = -1;
+  CUM_TRY(hipGetDevice(&dev));
+  if (dev != c->device) return CUM_EINVAL;
+  void* stage = nullptr;
+  CUM_TRY(noalloc_stage(&stage));
+  c->no_events = true;
+  int rc = update_impl(c, X_new, X_old, p, (char*)stage);
+  c->no_events = false;
+  // the staging array is shared by every call on this device: the update
+  // has finished reading it when this returns
+  if (rc == CUM_OK) CUM_TRY(hipStreamSynchronize(c->stream));
+  return rc;
 }
 
 int cum_recompute(cum_ctx* c, const void* X) {
