@@ -223,10 +223,12 @@ int cum_profile_read(cum_ctx *ctx, int64_t *launches, double *total_ms);
  *                           (2^(|I|-1) - 1 terms: the moment-cumulant
  *                           relation grouped by the part that holds the first
  *                           position; the same value up to FP64 rounding)
- * The recursion runs in the fused combine, which stages each order-d block's
- * lower-order sub-blocks in 64 KB of LDS: CUM_ESIZE when
- * ((b+1)^d - 1 - b^d) * 16 bytes exceed that (e.g. d = 6 with b = 4).  A
- * batch (below) uses each member's method as set when the batch was created.
+ * Both run in the fused combine when each order-d block's lower-order
+ * sub-blocks fit its 64 KB of LDS, else order by order (e.g. d = 6 with
+ * b = 4), where the recursion reads the moments m_{I\B} from the
+ * lower-order running sums.  A batch (below) uses each member's method as
+ * set when the batch was created for members whose sub-blocks fit, and
+ * Alg. 4 for the others.
  */
 enum { CUM_COMBINE_PARTITIONS = 0, CUM_COMBINE_RECURSION = 1 };
 int cum_set_combine(cum_ctx *ctx, int method);

@@ -310,10 +310,15 @@ int run_combine_and_norms(cum_ctx* c) {
     a.s_hi = c->s_hi[s];
     a.s_lo = c->s_lo[s];
     a.inv_t = 1.0 / (double)c->t;
-    for (int q = 1; q < s; ++q) a.C[q] = c->C[q];
+    for (int q = 1; q < s; ++q) {
+      a.C[q] = c->C[q];
+      a.Shi[q] = c->s_hi[q];
+      a.Slo[q] = c->s_lo[q];
+    }
     a.Cout = c->C[s];
     a.mult = c->mult[s];
     a.partial = c->partial[s];
+    a.rec = c->combine == CUM_COMBINE_RECURSION;
     Timed tm(c, 1);
     CUM_TRY(launch_combine(c->prec, s, a, c->T.ord[s].nblocks, c->stream));
   }
@@ -800,7 +805,6 @@ int cum_set_combine(cum_ctx* c, int method) {
   if (!c) return CUM_EINVAL;
   if (!c->ready) return CUM_ESTATE;
   if (method != CUM_COMBINE_PARTITIONS && method != CUM_COMBINE_RECURSION) return CUM_EINVAL;
-  if (method == CUM_COMBINE_RECURSION && c->lat_lds == 0) return CUM_ESIZE;
   c->combine = method;
   return CUM_OK;
 }
@@ -885,7 +889,7 @@ int batch_launch_all(cum_batch* bt) {
     CUM_TRY(launch_combine_lattice_batch(bt->prec, g.d, bt->d_lat, g.items, g.n, g.grid, g.lds, bt->stream));
   for (int s = 1; s <= CUM_MAXD; ++s)
     CUM_TRY(launch_combine_batch(bt->prec, s, bt->d_comb[s], bt->comb_items[s], bt->ncomb[s], bt->comb_grid[s],
-                                 bt->stage_bytes[s], bt->stream));
+                                 bt->stage_bytes[s], false, bt->stream));
   CUM_TRY(launch_norms_batch(bt->d_norm, (int)bt->ctx.size(), bt->stream));
   return CUM_OK;
 }
@@ -994,8 +998,9 @@ int cum_batch_create(cum_batch** out, cum_ctx* const* ctxs, int m) {
       }
     }
   }
-  // per-order combine of the other members: one entry per context (unused
-  // when d < s or the member uses the fused combine)
+  // per-order combine of the other members (Alg. 4's partition sum): one
+  // entry per context (unused when d < s or the member uses the fused
+  // combine)
   for (int s = 1; s <= CUM_MAXD; ++s) {
     std::vector<CombArgs> args((size_t)m);
     std::vector<int64_t> items;

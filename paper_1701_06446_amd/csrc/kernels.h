@@ -62,6 +62,12 @@ struct CombArgs {
   double* Cout;             // order-s cumulants
   const double* mult;       // per-block multiplicity
   double* partial;          // per-block mult * sum(c^2)
+  // recursion (rec = 1): c_I = m_I - sum over the proper subsets B holding
+  // I's first position of c_B m_{I\B}, with the moments m of the lower
+  // orders from their running sums (pairs)
+  int rec;
+  const void* Shi[CUM_MAXD + 1];
+  const void* Slo[CUM_MAXD + 1];
 };
 
 // Fused combine of every order (one workgroup per order-d block): the
@@ -116,8 +122,9 @@ hipError_t launch_update_batch(int prec, int str, bool vl, int kmax, const UpdAr
 bool update_quad_batch_supported(int prec, int str);
 hipError_t launch_update_quad_batch(int prec, int str, int kmax, const UpdArgs* ctxs, const UpdItem* items,
                                     int nitems, int grid, hipStream_t st);
+// rec: every listed member uses the recursion (their CombArgs have rec = 1)
 hipError_t launch_combine_batch(int prec, int s, const CombArgs* ctxs, const int64_t* items, int nitems,
-                                int grid, size_t stage_bytes, hipStream_t st);
+                                int grid, size_t stage_bytes, bool rec, hipStream_t st);
 hipError_t launch_norms_batch(const NormArgs* ctxs, int m, hipStream_t st);
 
 }  // namespace cum

@@ -625,9 +625,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_B
 // sub-blocks C_|B|(j_B) of the block (every non-empty proper subset B of the
 // S positions) are staged in LDS when they fit (STAGE), else gathered from
 // global memory.  Each element is c = S_s/t - (sum over partitions of
-// {1..S} into 2..S parts of prod_B c_B), Alg. 3/4.  The block's weighted
-// sum of squares (Alg. 5) goes to partial[blk].
-template <int S, typename St, bool STAGE>
+// {1..S} into 2..S parts of prod_B c_B), Alg. 3/4; or, with REC, c = S_s/t
+// - (sum over the proper B holding the first position of c_B m_{rest}),
+// where the sub-blocks without the first position hold moments instead.
+// The block's weighted sum of squares (Alg. 5) goes to partial[blk].
+template <int S, typename St, bool STAGE, bool REC>
 __device__ void combine_block(const CombArgs& a, int64_t blk, double* stage) {
   constexpr int NM = 1 << S;
   constexpr int FULL = NM - 1;
@@ -660,12 +662,21 @@ __device__ void combine_block(const CombArgs& a, int64_t blk, double* stage) {
     subbase[tid] = (int64_t)a.subrank[blk * NM + tid] * bl;
   }
   __syncthreads();
+  // value of the lower-order sub-block of `mask` at element offset o: its
+  // cumulant, or with REC and the first position outside the mask, its
+  // moment
+  auto sub_value = [&](int mask, int64_t o) __attribute__((always_inline)) -> double {
+    const int q = __builtin_popcount(mask);
+    if (REC && !(mask & 1))
+      return ((double)((const St*)a.Shi[q])[o] + (double)((const St*)a.Slo[q])[o]) * a.inv_t;
+    return a.C[q][o];
+  };
   if constexpr (STAGE) {
     const int total = lds_off[FULL];
     for (int i = tid; i < total; i += 256) {
       int mask = 1;
       while (mask + 1 < FULL && lds_off[mask + 1] <= i) ++mask;
-      stage[i] = a.C[__builtin_popcount(mask)][subbase[mask] + (i - lds_off[mask])];
+      stage[i] = sub_value(mask, subbase[mask] + (i - lds_off[mask]));
     }
     __syncthreads();
   }
@@ -696,10 +707,12 @@ __device__ void combine_block(const CombArgs& a, int64_t blk, double* stage) {
       if constexpr (STAGE) {
         cB[mask] = stage[lds_off[mask] + off];
       } else {
-        cB[mask] = a.C[__builtin_popcount(mask)][subbase[mask] + off];
+        cB[mask] = sub_value(mask, subbase[mask] + off);
       }
     }
-    const double A = partition_sum<S>(cB);
+    double A;
+    if constexpr (REC) A = recursion_sum<S>(cB);
+    else A = partition_sum<S>(cB);
     const int64_t o = blk * a.bs + e;
     const double mval = (e == tid) ? m0 : ((double)shi[o] + (double)slo[o]) * a.inv_t;
     const double c = mval - A;
@@ -713,21 +726,22 @@ __device__ void combine_block(const CombArgs& a, int64_t blk, double* stage) {
   if (tid == 0) a.partial[blk] = a.mult[blk] * (((red[0] + red[1]) + red[2]) + red[3]);
 }
 
-template <int S, typename St, bool STAGE>
+template <int S, typename St, bool STAGE, bool REC>
 __global__ __launch_bounds__(256) void k_combine(CombArgs a) {
   extern __shared__ __attribute__((aligned(16))) double stage[];
-  combine_block<S, St, STAGE>(a, blockIdx.x, stage);
+  combine_block<S, St, STAGE, REC>(a, blockIdx.x, stage);
 }
 
-// Batched form: items[i] = (context << 40) | block, for one order S.
-template <int S, typename St, bool STAGE>
+// Batched form: items[i] = (context << 40) | block, for one order S (the
+// members of one launch share the formula).
+template <int S, typename St, bool STAGE, bool REC>
 __global__ __launch_bounds__(256) void k_combine_batch(const CombArgs* __restrict__ ctxs,
                                                        const int64_t* __restrict__ items, int nitems) {
   extern __shared__ __attribute__((aligned(16))) double stage[];
   for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
     const int64_t w = items[i];
     const CombArgs a = ctxs[w >> 40];
-    combine_block<S, St, STAGE>(a, w & ((int64_t(1) << 40) - 1), stage);
+    combine_block<S, St, STAGE, REC>(a, w & ((int64_t(1) << 40) - 1), stage);
     __syncthreads();
   }
 }
@@ -1898,8 +1912,13 @@ static hipError_t launch_combine_s(const CombArgs& a, int64_t nblocks, hipStream
   for (int q = 0; q < S; ++q) { tot *= (a.b + 1); bs *= a.b; }
   tot = tot - 1 - bs;
   const size_t bytes = (size_t)tot * sizeof(double);
-  if (bytes <= COMB_STAGE_BYTES) hipLaunchKernelGGL((k_combine<S, St, true>), grid, blk, bytes, st, a);
-  else hipLaunchKernelGGL((k_combine<S, St, false>), grid, blk, 0, st, a);
+  if (bytes <= COMB_STAGE_BYTES) {
+    if (a.rec) hipLaunchKernelGGL((k_combine<S, St, true, true>), grid, blk, bytes, st, a);
+    else hipLaunchKernelGGL((k_combine<S, St, true, false>), grid, blk, bytes, st, a);
+  } else {
+    if (a.rec) hipLaunchKernelGGL((k_combine<S, St, false, true>), grid, blk, 0, st, a);
+    else hipLaunchKernelGGL((k_combine<S, St, false, false>), grid, blk, 0, st, a);
+  }
   return hipGetLastError();
 }
 
@@ -1924,33 +1943,42 @@ hipError_t launch_combine(int prec, int s, const CombArgs& a, int64_t nblocks, h
 
 template <int S, typename St>
 static hipError_t launch_combine_batch_s(const CombArgs* ctxs, const int64_t* items, int nitems, int grid,
-                                         size_t stage_bytes, hipStream_t st) {
-  if (stage_bytes <= COMB_STAGE_BYTES)
-    hipLaunchKernelGGL((k_combine_batch<S, St, true>), dim3(grid), dim3(256), stage_bytes, st, ctxs, items, nitems);
-  else
-    hipLaunchKernelGGL((k_combine_batch<S, St, false>), dim3(grid), dim3(256), 0, st, ctxs, items, nitems);
+                                         size_t stage_bytes, bool rec, hipStream_t st) {
+  if (stage_bytes <= COMB_STAGE_BYTES) {
+    if (rec)
+      hipLaunchKernelGGL((k_combine_batch<S, St, true, true>), dim3(grid), dim3(256), stage_bytes, st, ctxs, items,
+                         nitems);
+    else
+      hipLaunchKernelGGL((k_combine_batch<S, St, true, false>), dim3(grid), dim3(256), stage_bytes, st, ctxs, items,
+                         nitems);
+  } else {
+    if (rec)
+      hipLaunchKernelGGL((k_combine_batch<S, St, false, true>), dim3(grid), dim3(256), 0, st, ctxs, items, nitems);
+    else
+      hipLaunchKernelGGL((k_combine_batch<S, St, false, false>), dim3(grid), dim3(256), 0, st, ctxs, items, nitems);
+  }
   return hipGetLastError();
 }
 
 template <typename St>
 static hipError_t launch_combine_batch_t(int s, const CombArgs* ctxs, const int64_t* items, int nitems, int grid,
-                                         size_t stage_bytes, hipStream_t st) {
+                                         size_t stage_bytes, bool rec, hipStream_t st) {
   switch (s) {
-    case 1: return launch_combine_batch_s<1, St>(ctxs, items, nitems, grid, stage_bytes, st);
-    case 2: return launch_combine_batch_s<2, St>(ctxs, items, nitems, grid, stage_bytes, st);
-    case 3: return launch_combine_batch_s<3, St>(ctxs, items, nitems, grid, stage_bytes, st);
-    case 4: return launch_combine_batch_s<4, St>(ctxs, items, nitems, grid, stage_bytes, st);
-    case 5: return launch_combine_batch_s<5, St>(ctxs, items, nitems, grid, stage_bytes, st);
-    case 6: return launch_combine_batch_s<6, St>(ctxs, items, nitems, grid, stage_bytes, st);
+    case 1: return launch_combine_batch_s<1, St>(ctxs, items, nitems, grid, stage_bytes, rec, st);
+    case 2: return launch_combine_batch_s<2, St>(ctxs, items, nitems, grid, stage_bytes, rec, st);
+    case 3: return launch_combine_batch_s<3, St>(ctxs, items, nitems, grid, stage_bytes, rec, st);
+    case 4: return launch_combine_batch_s<4, St>(ctxs, items, nitems, grid, stage_bytes, rec, st);
+    case 5: return launch_combine_batch_s<5, St>(ctxs, items, nitems, grid, stage_bytes, rec, st);
+    case 6: return launch_combine_batch_s<6, St>(ctxs, items, nitems, grid, stage_bytes, rec, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_combine_batch(int prec, int s, const CombArgs* ctxs, const int64_t* items, int nitems,
-                                int grid, size_t stage_bytes, hipStream_t st) {
+                                int grid, size_t stage_bytes, bool rec, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
-  if (prec == PREC_F64) return launch_combine_batch_t<double>(s, ctxs, items, nitems, grid, stage_bytes, st);
-  return launch_combine_batch_t<float>(s, ctxs, items, nitems, grid, stage_bytes, st);
+  if (prec == PREC_F64) return launch_combine_batch_t<double>(s, ctxs, items, nitems, grid, stage_bytes, rec, st);
+  return launch_combine_batch_t<float>(s, ctxs, items, nitems, grid, stage_bytes, rec, st);
 }
 
 hipError_t launch_norms_batch(const NormArgs* ctxs, int m, hipStream_t st) {

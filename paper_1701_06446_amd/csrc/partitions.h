@@ -67,4 +67,16 @@ __device__ __forceinline__ double partition_sum(const double (&cB)[1 << S]) {
   return A;
 }
 
+// The recursion's subtracted sum for one element: over the proper subsets B
+// of {1..S} that hold position 1 (bit 0), the cumulant c_B times the moment
+// of the other positions (cm[B] holds c_B when B has bit 0, else m_B).
+template <int S>
+__device__ __forceinline__ double recursion_sum(const double (&cm)[1 << S]) {
+  constexpr int FULL = (1 << S) - 1;
+  double A = 0.0;
+#pragma unroll
+  for (int q = 1; q < FULL; q += 2) A += cm[q] * cm[FULL & ~q];
+  return A;
+}
+
 }  // namespace cum

@@ -1,9 +1,10 @@
-"""The fused combine (every order in one launch over each order-d block's
-sub-block lattice) and its two formulas: Alg. 4's partition sum and the
+"""The combine (every order in one launch over each order-d block's
+sub-block lattice, or order by order) and its two formulas: Alg. 4's partition sum and the
 recursion c_I = m_I - sum_{B holding I's first position} c_B m_{I\\B}.  Both
 against the FP64 oracle (which follows Alg. 4 on the plain definition) on
 shapes that use the lattice (d = 2..6 with small b, b not a power of two,
-b not dividing n, b = 8) and against each other."""
+b not dividing n, b = 8), on shapes combined order by order, and against
+each other."""
 import numpy as np
 import pytest
 
@@ -62,15 +63,17 @@ def test_partitions_and_recursion_vs_oracle(shape, prec):
     cum.cum_free(rec)
 
 
-def test_recursion_needs_the_lattice_in_lds():
-    """d=6, b=4: (5^6 - 1 - 4^6) * 16 bytes exceed 64 KB, so the per-order
-    combine runs and the recursion is refused."""
-    import paper_1701_06446_amd as cum
+PER_ORDER = [  # n, d, b, t, p: lattices beyond the 64 KB of LDS, combined order by order
+    (24, 6, 4, 600, 100),
+    (16, 5, 8, 600, 100),
+]
 
-    rows = to_device(as_input(_rows(24, 300, 10, 0, 5), "fp32"))
-    ctx = cum.cum_init(24, 6, 4, rows)
-    with pytest.raises(cum.CumError) as e:
-        cum.cum_set_combine(ctx, "recursion")
-    assert e.value.status == cum.CUM_ESIZE
-    cum.cum_set_combine(ctx, "partitions")
-    cum.cum_free(ctx)
+
+@pytest.mark.parametrize("shape", PER_ORDER, ids=lambda s: "n%d_d%d_b%d" % s[:3])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_per_order_partitions_and_recursion_vs_oracle(shape, prec):
+    """d = 6 with b = 4 and d = 5 with b = 8: the lattice does not fit, so
+    each order is combined on its own (lower-order sub-blocks staged where
+    they fit in LDS, gathered otherwise); the recursion takes the moments
+    of the sub-blocks without the first position from the running sums."""
+    test_partitions_and_recursion_vs_oracle(shape, prec)
