@@ -9,8 +9,15 @@ GPU, with the stream's rows already resident in HBM.
 
 Prints one JSON line: rows/s of the main path (--prec, default fp32) as
 `value`, the per-path figures (fp64, fp32, split-bf16x3) with their sampled
-error against the FP64 oracle, the dominant kernel's roofline, and the
-oracle's own throughput on the host cores (cpu_baseline).
+error against the FP64 oracle, the dominant kernel's roofline, the oracle's
+own throughput on the host cores (cpu_baseline), and further legs: the
+200-step trajectory of the regime-change stream, the order-6 precision
+sweep, the adjoint, 64 batched streams and the paper-scale nu_4 study.
+
+The oracle runs only in the cpu_baseline leg: the GPU legs record sampled
+stored elements (random pyramid offsets and the GPU's values there) and the
+window they belong to, and that leg computes the oracle's values at those
+elements and states each error.
 """
 from __future__ import annotations
 
@@ -81,21 +88,24 @@ def algorithmic_flops_per_update(p: int) -> float:
     return 2.0 * (2 * p) * sum(cum.cum_num_elems(N, B, k) for k in range(1, D + 1))
 
 
-def sampled_error(ctx, window: np.ndarray, rng, count: int = 40):
-    """Relative error of the GPU cumulants against the per-element FP64 oracle
-    on sampled stored elements of orders 2..d (Frobenius over the sample)."""
-    import paper_1701_06446_amd as cum
-    from oracle.element import cumulant_at, sample_elements
+# Deferred accuracy checks: (label, window rows, n, b, d, {k: (offsets,
+# GPU values)}, tolerance), evaluated against the oracle in the cpu_baseline
+# leg.
+CHECKS = []
 
-    cache = {}
-    worst = 0.0
-    for k in range(2, D + 1):
-        g = cum.cum_get(ctx, k)
-        offs, idxs = sample_elements(N, B, k, count, rng)
-        ref = np.array([cumulant_at(window, idx, cache) for idx in idxs])
-        err = np.linalg.norm(g[offs] - ref) / max(np.linalg.norm(ref), 1e-300)
-        worst = max(worst, float(err))
-    return worst
+
+def record_check(label, ctx, window, n, b, d, rng, count=40, tol=None):
+    """Samples `count` random stored elements of every order 2..d of ctx's
+    cumulants (random pyramid offsets) and keeps them, with a host copy of
+    the window, for the oracle comparison of the cpu_baseline leg."""
+    import paper_1701_06446_amd as cum
+
+    samples = {}
+    for k in range(2, d + 1):
+        ne = cum.cum_num_elems(n, b, k)
+        offs = rng.integers(0, ne, size=count)
+        samples[k] = (offs, cum.cum_get(ctx, k)[offs])
+    CHECKS.append((label, np.asarray(window, dtype=np.float64), n, b, d, samples, tol))
 
 
 def run_path(path, s, warmup, steps, check, host_leg=False):
@@ -187,9 +197,7 @@ def run_path(path, s, warmup, steps, check, host_leg=False):
     out["speedup_vs_recompute"] = rec_ms / out["ms_per_step_without_kernel_events"]
     out["speedup_theory"] = T / ((1 if mode == "fifo" else 2) * P + 15)  # B(4) = 15
     if check:
-        window = rows[w * P: w * P + T].astype(np.float64)
-        out["err_sampled"] = sampled_error(ctx, window, np.random.default_rng(7))
-        out["tol"] = TOL[prec]
+        record_check("paths." + path, ctx, rows[w * P: w * P + T], N, B, D, np.random.default_rng(7), tol=TOL[prec])
     if mode == "fifo":
         out["fifo_slots"] = T // P
     cum.cum_free(ctx)
@@ -205,7 +213,6 @@ def run_batched(steps, warmup, prec="fp32", autotune=True):
 
     import paper_1701_06446_amd as cum
     import streams
-    from oracle.element import cumulant_at, sample_elements
     from paper_1701_06446_amd import autotune as at
 
     ss = streams.batched_streams(m=64, steps=warmup + steps)
@@ -241,16 +248,10 @@ def run_batched(steps, warmup, prec="fp32", autotune=True):
     flops = sum(2.0 * 2 * s.p * sum(cum.cum_num_elems(s.n, s.b, k) for k in range(1, s.d + 1)) for s in ss)
     flops_distinct = sum(2.0 * 2 * s.p * at.distinct_elements(s.n, s.d) for s in ss)
     rng = np.random.default_rng(5)
-    worst = 0.0
     for i in range(0, 64, 8):
         s = ss[i]
-        window = rows[i][w * s.p:w * s.p + s.t].astype(np.float64)
-        cache = {}
-        for k in range(2, s.d + 1):
-            offs, idxs = sample_elements(s.n, s.b, k, 6, rng)
-            ref = np.array([cumulant_at(window, idx, cache) for idx in idxs])
-            g = cum.cum_get(ctxs[i], k)[offs]
-            worst = max(worst, float(np.linalg.norm(g - ref) / np.linalg.norm(ref)))
+        record_check("batched.stream%02d" % i, ctxs[i], rows[i][w * s.p:w * s.p + s.t], s.n, s.b, s.d, rng,
+                     count=6, tol=TOL[prec])
     cum.cum_batch_free(bt)
     for c in ctxs:
         cum.cum_free(c)
@@ -260,62 +261,162 @@ def run_batched(steps, warmup, prec="fp32", autotune=True):
             "tflops_algorithmic": flops * steps / el / 1e12,
             "tflops_distinct_elements": flops_distinct * steps / el / 1e12,
             "b_choice": {str(b): sum(1 for s in ss if s.b == b) for b in (1, 2, 4, 8)},
-            "autotune_s": tune_s, "err_sampled_max": worst, "tol": TOL[prec]}
+            "autotune_s": tune_s, "tol": TOL[prec]}
 
 
-def run_order6(steps=4, warmup=1):
-    """The order-6 workload: mixed Exp(1) sources, n=48, d=6, b=4, t=50000,
-    p=2000, fp32 sliding mode; per-kernel times from the event profiler and
-    the sampled error against the per-element FP64 oracle."""
+def run_order6(steps=50, warmup=1, paths=("fp32", "fp64", "bf16x3", "fp32-recursion")):
+    """The high-order precision sweep: mixed Exp(1) sources, n=48, d=6, b=4,
+    t=50000, p=2000, sliding mode, `steps` updates per path (FP32, FP64 and
+    split-BF16x3 contractions with Alg. 4's combine, and FP32 with the
+    recursion combine); per-kernel times from the event profiler, sampled
+    errors against the oracle (cpu_baseline leg), and the norms beside their
+    population values: the sources' cumulant tensors are diagonal with
+    (k-1)! entries and the mixing is orthogonal, so ||C_k||_F tends to
+    sqrt(48) (k-1)! (sampling noise is large at k = 5, 6)."""
+    import math
+
     import torch
 
     import paper_1701_06446_amd as cum
     import streams
-    from oracle.element import cumulant_at, sample_elements
 
     n, d, b, t, p = 48, 6, 4, 50000, 2000
     s = streams.mixed_exp_stream(steps=warmup + steps)
-    rows = np.ascontiguousarray(s.rows.astype(np.float32))
-    dev = torch.from_numpy(rows).to("cuda")
-    t0 = time.perf_counter()
-    ctx = cum.cum_init(n, d, b, dev[:t])
-    init_s = time.perf_counter() - t0
-    w = 0
-
-    def step():
-        nonlocal w
-        w += 1
-        cum.cum_update(ctx, dev[t + (w - 1) * p:t + w * p], dev[(w - 1) * p:w * p])
-
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
-    cum.cum_profile_enable(ctx, True)
-    t1 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    cum.cum_sync(ctx)  # the last step's norms
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t1
-    prof = cum.cum_profile_read(ctx)
-    cum.cum_profile_enable(ctx, False)
+    out = {"workload": "mixed Exp(1) sources S W, n=48 d=6 b=4 t=50000 p=2000, sliding",
+           "steps": steps, "population_fro": [None, None] + [math.sqrt(n) * math.factorial(k - 1)
+                                                             for k in range(2, d + 1)]}
     elems = [cum.cum_num_elems(n, b, k) for k in range(1, d + 1)]
     flops = 2.0 * 2 * p * sum(elems)
-    upd_ms = prof["update"][1] / prof["update"][0]
-    window = rows[w * p:w * p + t].astype(np.float64)
-    rng = np.random.default_rng(17)
-    cache, worst = {}, 0.0
-    for k in range(2, d + 1):
-        offs, idxs = sample_elements(n, b, k, 12, rng)
-        ref = np.array([cumulant_at(window, idx, cache) for idx in idxs])
-        worst = max(worst, float(np.linalg.norm(cum.cum_get(ctx, k)[offs] - ref) / np.linalg.norm(ref)))
+    out["flops_per_update"] = flops
+    out["stored_elements"] = sum(elems)
+    for path in paths:
+        prec, _, method = path.partition("-")
+        rows = np.ascontiguousarray(s.rows.astype(np.float64 if prec == "fp64" else np.float32))
+        dev = torch.from_numpy(rows).to("cuda")
+        t0 = time.perf_counter()
+        ctx = cum.cum_init(n, d, b, dev[:t], prec=prec)
+        cum.cum_sync(ctx)
+        init_s = time.perf_counter() - t0
+        if method:
+            cum.cum_set_combine(ctx, method)
+        w = 0
+
+        def step():
+            nonlocal w
+            w += 1
+            cum.cum_update(ctx, dev[t + (w - 1) * p:t + w * p], dev[(w - 1) * p:w * p])
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        cum.cum_profile_enable(ctx, True)
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        cum.cum_sync(ctx)  # the last step's norms
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        prof = cum.cum_profile_read(ctx)
+        cum.cum_profile_enable(ctx, False)
+        upd_ms = prof["update"][1] / prof["update"][0]
+        fro, nu = cum.cum_norms(ctx)
+        record_check("order6." + path, ctx, rows[w * p:w * p + t], n, b, d, np.random.default_rng(17), count=12,
+                     tol=TOL[prec])
+        out[path] = {"ms_per_step": el / steps * 1e3, "rows_per_s": steps * p / el,
+                     # launches per step: one update; the combine order by order (6)
+                     "kernel_ms_per_step": {k: v[1] / steps for k, v in prof.items() if v[0]},
+                     "launches_per_step": {k: v[0] / steps for k, v in prof.items() if v[0]},
+                     "update_ms": upd_ms,
+                     "update_tflops": flops / (upd_ms * 1e-3) / 1e12,
+                     "update_frac_peak": flops / (upd_ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec],
+                     "init_s": init_s, "fro": [None if not np.isfinite(f) else f for f in fro],
+                     "tol": TOL[prec]}
+        cum.cum_free(ctx)
+        del dev
+        torch.cuda.empty_cache()
+    return out
+
+
+def run_trajectory(s, steps=200, switch=100, prec="fp32"):
+    """The regime-change stream's 200 steps (the first `switch` Gaussian,
+    the rest copula rows) with every step's norms read back synchronously
+    (the emit of Alg. 1, Sec. 2.2): ||C_3||, ||C_4||, nu_3, nu_4 per step,
+    the synchronous step latency, and sampled oracle checks at the last
+    Gaussian step and the last step."""
+    import torch
+
+    import paper_1701_06446_amd as cum
+
+    rows = np.ascontiguousarray(s.rows[:T + steps * P].astype(np.float32))
+    dev = torch.from_numpy(rows).to("cuda")
+    ctx = cum.cum_init(N, D, B, dev[:T], prec=prec)
+    traj = {"fro3": [], "fro4": [], "nu3": [], "nu4": []}
+    t0 = time.perf_counter()
+    for w in range(1, steps + 1):
+        cum.cum_update(ctx, dev[T + (w - 1) * P:T + w * P], dev[(w - 1) * P:w * P])
+        fro, nu = cum.cum_norms(ctx)
+        traj["fro3"].append(float("%.6g" % fro[3]))
+        traj["fro4"].append(float("%.6g" % fro[4]))
+        traj["nu3"].append(float("%.6g" % nu[3]))
+        traj["nu4"].append(float("%.6g" % nu[4]))
+        if w in (switch, steps):
+            t0 -= time.perf_counter()
+            record_check("trajectory.step%d" % w, ctx, rows[w * P:w * P + T], N, B, D, np.random.default_rng(w),
+                         count=30, tol=TOL[prec])
+            t0 += time.perf_counter()
+    el = time.perf_counter() - t0
     cum.cum_free(ctx)
-    return {"workload": "mixed Exp(1) sources S W, n=48 d=6 b=4 t=50000 p=2000, fp32 sliding",
-            "steps": steps, "ms_per_step": el / steps * 1e3, "rows_per_s": steps * p / el,
-            "kernel_ms": {k: v[1] / v[0] for k, v in prof.items() if v[0]},
-            "update_tflops": flops / (upd_ms * 1e-3) / 1e12, "update_frac_fp32_peak": flops / (upd_ms * 1e-3) / 1e12 / 157.3,
-            "flops_per_update": flops, "stored_elements": sum(elems), "init_s": init_s,
-            "err_sampled": worst, "tol": TOL["fp32"]}
+    nu4 = np.array(traj["nu4"])
+    return {"workload": "regime-change stream n=60 d=4 b=4 t=20000 p=1000, %d steps, copula rows after "
+                        "step %d" % (steps, switch), "prec": prec,
+            "ms_per_step_with_norms_readback": el / steps * 1e3,
+            "nu4_gaussian_steps_mean": float(nu4[:switch].mean()),
+            "nu4_after_window_turnover_mean": float(nu4[switch + T // P:].mean()) if steps > switch + T // P else None,
+            "turnover_steps": T // P, **traj}
+
+
+def run_nu4_study(runs=100, n=100, t=1_000_000, tup=25_000, windows=61):
+    """The paper's stream statistics study (Sec. 4.3) at its scale: n = 100,
+    t = 10^6, t_up = 2.5 10^4, 61 windows, the first Gaussian, the updates
+    from a Student-t copula (nu = 10) with the first window's Gaussian
+    marginals, `runs` seeded repetitions on the fp32 path (d = 4, b = 4).
+    nu_3 and nu_4 per window for the first run; the 5th, 50th and 95th
+    percentiles of nu_4 at window 1 (Gaussian) and window 61 (no Gaussian
+    row left after window 41) over the runs, beside the paper's (its
+    covariance is not given: context only)."""
+    import torch
+
+    import paper_1701_06446_amd as cum
+    import streams
+
+    nu_first, nu_last, curve = [], [], {"nu3": [], "nu4": []}
+    t0 = time.perf_counter()
+    for r in range(runs):
+        X, _ = streams.tcopula_study_rows(r, n=n, t=t, tup=tup, windows=windows)
+        ctx = cum.cum_init(n, 4, 4, X[:t], prec="fp32")
+        _, nu = cum.cum_norms(ctx)
+        nu_first.append(nu[4])
+        if r == 0:
+            curve["nu3"].append(float("%.5g" % nu[3]))
+            curve["nu4"].append(float("%.5g" % nu[4]))
+        for w in range(2, windows + 1):
+            lo = (w - 2) * tup
+            cum.cum_update(ctx, X[t + lo:t + lo + tup], X[lo:lo + tup])
+            if r == 0:
+                _, nu = cum.cum_norms(ctx)
+                curve["nu3"].append(float("%.5g" % nu[3]))
+                curve["nu4"].append(float("%.5g" % nu[4]))
+        _, nu = cum.cum_norms(ctx)
+        nu_last.append(nu[4])
+        cum.cum_free(ctx)
+        del X
+    el = time.perf_counter() - t0
+    q = lambda v: [float("%.4g" % x) for x in np.percentile(np.array(v), [5, 50, 95])]
+    return {"workload": "n=%d t=%d t_up=%d, %d windows: Gaussian, then Student-t copula (nu=10) with "
+                        "Gaussian marginals; d=4 b=4 fp32" % (n, t, tup, windows),
+            "runs": runs, "seconds": el, "first_run": curve,
+            "nu4_quantiles_5_50_95": {"window_1": q(nu_first), "window_%d" % windows: q(nu_last)},
+            "paper_nu4_quantiles_5_50_95": {"gaussian": [0.004, 0.006, 0.011], "t_copula": [0.199, 0.209, 0.220]}}
 
 
 def run_adjoint(reps=5):
@@ -342,22 +443,68 @@ def run_adjoint(reps=5):
 def cpu_baseline(s, budget_s=12.0):
     """The oracle (as it stands) on the host cores: sliding steps of p=1000 rows
     at n=60, d=4, b=4 from a 2000-row start window, each step = compensated
-    sums + Alg. 4 combine + Alg. 5 norms."""
+    sums + Alg. 4 combine + Alg. 5 norms; on all the cores the oracle's
+    OpenMP loops use, and on one core (in a child process)."""
+    import subprocess
+
     import oracle
 
     rows = s.rows.astype(np.float32).astype(np.float64)
+    n_steps, el = cpu_timed(rows, budget_s, 30)
+    out = {"value": n_steps * P / el, "unit": "rows/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": "%d sliding steps of p=1000 rows (n=60,d=4,b=4) from a 2000-row start window; "
+                     "per step: FP64 compensated sums of orders 1..4, Alg.4 combine, Alg.5 norms; "
+                     "%.1f s" % (n_steps, el)}
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    code = ("import sys, json, time; sys.path.insert(0, %r); import numpy as np; import bench, streams; "
+            "s = streams.regime_change_stream(steps=8, switch=8); "
+            "rows = s.rows.astype(np.float32).astype(np.float64); "
+            "import oracle; n, el = bench.cpu_timed(rows, 2, 6); "
+            "print(json.dumps([n, el, oracle.num_threads()]))" % ROOT)
+    try:
+        res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+        n1, el1, th1 = json.loads(res.stdout.strip().splitlines()[-1])
+        out["one_core"] = {"value": n1 * P / el1, "unit": "rows/s", "cores": th1,
+                           "sample": "%d sliding steps, the same per-step work; %.1f s" % (n1, el1)}
+    except (subprocess.SubprocessError, ValueError, IndexError) as e:
+        out["one_core"] = {"error": str(e)}
+    return out
+
+
+def cpu_timed(rows, budget, max_steps):
+    """Oracle sliding steps on `rows` for about `budget` seconds (at least 2
+    steps, at most max_steps): (steps, seconds)."""
+    import oracle
+
     o = oracle.SlidingOracle(rows[:2000], N, D, B)
     n_steps, t0 = 0, time.perf_counter()
-    while n_steps < 2 or (time.perf_counter() - t0 < budget_s and n_steps < 30):
+    while n_steps < 2 or (time.perf_counter() - t0 < budget and n_steps < max_steps):
         n_steps += 1
         lo, hi = (n_steps - 1) * P, n_steps * P
         o.update(rows[2000 + lo:2000 + hi], rows[lo:hi])
         oracle.norms(o.cumulants(), N, B)
-    el = time.perf_counter() - t0
-    return {"value": n_steps * P / el, "unit": "rows/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "%d sliding steps of p=1000 rows (n=60,d=4,b=4) from a 2000-row start window; "
-                      "per step: FP64 compensated sums of orders 1..4, Alg.4 combine, Alg.5 norms; "
-                      "%.1f s" % (n_steps, el)}
+    return n_steps, time.perf_counter() - t0
+
+
+def oracle_checks():
+    """The deferred checks against the oracle: for every recorded sample, the
+    oracle's cumulant at each sampled element (Alg. 4 on moments taken from
+    the same window) and the relative error over the sample."""
+    from oracle.element import cumulant_at, indices_of
+
+    out = {}
+    for label, window, n, b, d, samples, tol in CHECKS:
+        cache, worst = {}, 0.0
+        for k, (offs, vals) in samples.items():
+            idxs = indices_of(n, b, k, offs)
+            keep = [i for i, x in enumerate(idxs) if x is not None]
+            if not keep:
+                continue
+            ref = np.array([cumulant_at(window, idxs[i], cache) for i in keep])
+            err = np.linalg.norm(vals[keep] - ref) / max(np.linalg.norm(ref), 1e-300)
+            worst = max(worst, float(err))
+        out[label] = {"err_sampled": worst, "tol": tol}
+    return out
 
 
 def main():
@@ -374,6 +521,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-stream batched leg")
     ap.add_argument("--no-extra", action="store_true", help="skip the order-6 and adjoint legs")
+    ap.add_argument("--no-trajectory", action="store_true", help="skip the 200-step trajectory leg")
+    ap.add_argument("--order6-steps", type=int, default=50)
+    ap.add_argument("--nu4-runs", type=int, default=100,
+                    help="repetitions of the paper-scale nu_4 study (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -427,19 +578,38 @@ def main():
     }
     if args.copy_calibration:
         line["copy_calibration"] = copy_calibration(args.copy_calibration)
+    if not args.no_trajectory:
+        print("[bench] trajectory: 200 steps with norms read back", file=sys.stderr, flush=True)
+        line["trajectory"] = run_trajectory(s)
+        print("[bench] trajectory: %.3f ms/step" % line["trajectory"]["ms_per_step_with_norms_readback"],
+              file=sys.stderr, flush=True)
     if not args.no_extra:
-        print("[bench] order 6: n=48 d=6 b=4 p=2000", file=sys.stderr, flush=True)
-        line["order6"] = run_order6()
-        print("[bench] order 6: %.3f ms/step" % line["order6"]["ms_per_step"], file=sys.stderr, flush=True)
+        print("[bench] order 6: n=48 d=6 b=4 p=2000, %d steps per path" % args.order6_steps,
+              file=sys.stderr, flush=True)
+        line["order6"] = run_order6(steps=args.order6_steps)
+        for k in ("fp32", "fp64", "bf16x3", "fp32-recursion"):
+            print("[bench] order 6 %s: %.3f ms/step" % (k, line["order6"][k]["ms_per_step"]),
+                  file=sys.stderr, flush=True)
         print("[bench] adjoint", file=sys.stderr, flush=True)
         line["adjoint"] = run_adjoint()
     if not args.no_batched:
         print("[bench] batched: 64 streams, 40 steps", file=sys.stderr, flush=True)
         line["batched"] = run_batched(steps=40, warmup=3)
         print("[bench] batched: %.3f ms/step" % line["batched"]["ms_per_step"], file=sys.stderr, flush=True)
+    if args.nu4_runs > 0:
+        print("[bench] nu_4 study: %d runs" % args.nu4_runs, file=sys.stderr, flush=True)
+        line["nu4_study"] = run_nu4_study(runs=args.nu4_runs)
+        print("[bench] nu_4 study: %.1f s" % line["nu4_study"]["seconds"], file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(s)
+        print("[bench] oracle checks: %d samples" % len(CHECKS), file=sys.stderr, flush=True)
+        checks = oracle_checks()
+        line["oracle_checks"] = checks
+        for path, r in res.items():
+            if "paths." + path in checks:
+                r["err_sampled"] = checks["paths." + path]["err_sampled"]
+        line["oracle_checks_pass"] = all(c["err_sampled"] <= c["tol"] for c in checks.values())
     print(json.dumps(line))
 
 

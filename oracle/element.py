@@ -71,3 +71,23 @@ def sample_elements(n: int, b: int, k: int, count: int, rng) -> tuple:
         offs.append(r * b ** k + e)
         idxs.append(idx)
     return np.array(offs), idxs
+
+
+def indices_of(n: int, b: int, k: int, offs) -> list:
+    """Global multi-index of each stored order-k element at the pyramid
+    offsets `offs` (block r = off // b^k in lexicographic order, within-block
+    digits a_1..a_k, a_1 slowest), or None where an index is padding (>= n)."""
+    from . import tuples
+
+    tl = tuples(n, b, k)
+    out = []
+    for off in offs:
+        r, e = divmod(int(off), b ** k)
+        a = []
+        for _ in range(k):
+            e, am = divmod(e, b)
+            a.append(am)
+        a.reverse()
+        idx = [int(j) * b + am for j, am in zip(tl[r], a)]
+        out.append(idx if max(idx) < n else None)
+    return out

@@ -173,3 +173,57 @@ def adjoint_workload(t=10000, n=32, workload_id=4):
 def stream_by_name(name: str, **kw) -> Stream:
     return {"gaussian": gaussian_stream, "regime_change": regime_change_stream,
             "mixed_exp": mixed_exp_stream}[name](**kw)
+
+
+def _student_t_cdf_lower(t_abs, nu: int):
+    """P(T <= -|t|) for a Student-t with an even number nu of degrees of
+    freedom, in closed form: 1/2 - |t| / (2 sqrt(nu + t^2)) *
+    sum_{j < nu/2} (2j)! / (4^j j!^2) (nu / (nu + t^2))^j (torch, float64)."""
+    import torch
+
+    assert nu % 2 == 0 and nu > 0
+    r = nu / (nu + t_abs * t_abs)
+    term = torch.ones_like(t_abs)
+    acc = torch.ones_like(t_abs)
+    for j in range(1, nu // 2):
+        term = term * r * (2 * j - 1) / (2 * j)
+        acc = acc + term
+    return 0.5 - 0.5 * t_abs / torch.sqrt(nu + t_abs * t_abs) * acc
+
+
+def tcopula_study_rows(run: int, n=100, t=1_000_000, tup=25_000, windows=61, nu=10, device="cuda",
+                       workload_id=6):
+    """Rows of the paper-scale stream study on the GPU (torch, float32): the
+    first window of t rows i.i.d. N(0, Sigma), then (windows - 1) batches of
+    tup rows from a Student-t copula with nu degrees of freedom and the
+    correlation of Sigma, whose marginals are the first window's Gaussian
+    marginals N(0, Sigma_jj).  Sigma = A A^T / n + I with a seeded Gaussian A
+    (one Sigma for every run); each run draws from its own seeded generator.
+    t-copula rows: z ~ N(0, R), w ~ chi^2_nu (a sum of nu squared normals),
+    u_j = F_nu(z_j / sqrt(w / nu)), x_j = sqrt(Sigma_jj) Phi^{-1}(u_j), with
+    Phi^{-1}(F_nu(-|y|)) taken in the lower tail for precision."""
+    import torch
+
+    sigma = covariance(rng_for(workload_id), n)
+    sd = np.sqrt(np.diag(sigma))
+    L = torch.from_numpy(np.linalg.cholesky(sigma)).to(device)
+    Lr = torch.from_numpy(np.linalg.cholesky(sigma / np.outer(sd, sd))).to(device)
+    sdt = torch.from_numpy(sd).to(device)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(np.random.SeedSequence([SEED_ROOT, workload_id, 1, run]).generate_state(1)[0]))
+    m = (windows - 1) * tup
+    out = torch.empty((t + m, n), dtype=torch.float32, device=device)
+    step = 250_000
+    for lo in range(0, t, step):
+        hi = min(t, lo + step)
+        z = torch.randn((hi - lo, n), generator=g, device=device, dtype=torch.float64)
+        out[lo:hi] = (z @ L.T).float()
+    for lo in range(0, m, step):
+        hi = min(m, lo + step)
+        z = torch.randn((hi - lo, n), generator=g, device=device, dtype=torch.float64) @ Lr.T
+        w = (torch.randn((hi - lo, nu), generator=g, device=device, dtype=torch.float64) ** 2).sum(dim=1)
+        y = z / torch.sqrt(w / nu)[:, None]
+        lower = _student_t_cdf_lower(y.abs(), nu)
+        x = -torch.special.ndtri(lower) * torch.sign(y)
+        out[t + lo:t + hi] = (x * sdt).float()
+    return out, sigma

@@ -365,3 +365,38 @@ def test_element_oracle_matches_pyramid_oracle():
         offs, idxs = sample_elements(n, b, k, 25, rng)
         for o, idx in zip(offs, idxs):
             assert abs(C[k - 1][o] - cumulant_at(X, idx, cache)) <= 1e-12 * (1 + abs(C[k - 1][o]))
+
+
+def test_indices_of_inverts_sample_elements():
+    """The offset -> multi-index map agrees with the sampler's own pairs, and
+    padded elements map to None (n = 13, b = 4: columns 13..15 are padding)."""
+    from oracle.element import indices_of, sample_elements
+
+    rng = np.random.default_rng(0)
+    for n, b, k in [(13, 4, 3), (9, 2, 4), (6, 3, 2)]:
+        offs, idxs = sample_elements(n, b, k, 30, rng)
+        assert indices_of(n, b, k, offs) == idxs
+    import oracle
+
+    # order 2, n = 13, b = 4: blocks (j1 <= j2) of 16 elements; the
+    # elements with both indices < 13 are 13 * 13 minus the lower triangle
+    # of the off-diagonal blocks: sum over j1 < j2 of rows(j1) * rows(j2)
+    rows = [4, 4, 4, 1]
+    want = sum(rows[j] * rows[j] for j in range(4)) + sum(rows[i] * rows[j] for i in range(4) for j in range(i + 1, 4))
+    got = indices_of(13, 4, 2, range(oracle.pyramid_size(13, 4, 2)))
+    assert sum(1 for g in got if g is not None) == want
+
+
+def test_student_t_lower_tail_closed_form():
+    """The stream study's even-nu Student-t CDF (closed form) against
+    scipy's, in the range its samples fall in."""
+    import torch
+    from scipy import stats
+
+    import streams
+
+    t = torch.linspace(0.0, 10.0, 501, dtype=torch.float64)
+    for nu in (2, 4, 10):
+        got = streams._student_t_cdf_lower(t, nu).numpy()
+        ref = stats.t.cdf(-t.numpy(), nu)
+        assert np.max(np.abs(got - ref) / ref) < 1e-9, nu
