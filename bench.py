@@ -384,15 +384,19 @@ def run_nu4_study(runs=100, n=100, t=1_000_000, tup=25_000, windows=61):
     percentiles of nu_4 at window 1 (Gaussian) and window 61 (no Gaussian
     row left after window 41) over the runs, beside the paper's (its
     covariance is not given: context only)."""
-    import torch
+    import math
 
     import paper_1701_06446_amd as cum
     import streams
 
+    from tests.noise_floor import gaussian_noise_floor
+
     nu_first, nu_last, curve = [], [], {"nu3": [], "nu4": []}
     t0 = time.perf_counter()
     for r in range(runs):
-        X, _ = streams.tcopula_study_rows(r, n=n, t=t, tup=tup, windows=windows)
+        if r and r % 10 == 0:
+            print("[bench] nu_4 study: run %d" % r, file=sys.stderr, flush=True)
+        X, S = streams.tcopula_study_rows(r, n=n, t=t, tup=tup, windows=windows)
         ctx = cum.cum_init(n, 4, 4, X[:t], prec="fp32")
         _, nu = cum.cum_norms(ctx)
         nu_first.append(nu[4])
@@ -408,6 +412,11 @@ def run_nu4_study(runs=100, n=100, t=1_000_000, tup=25_000, windows=61):
                 curve["nu4"].append(float("%.5g" % nu[4]))
         _, nu = cum.cum_norms(ctx)
         nu_last.append(nu[4])
+        if r == 0:
+            t0 -= time.perf_counter()
+            record_check("nu4_study.run0.window%d" % windows, ctx, X[-t:].double().cpu().numpy(), n, 4, 4,
+                         np.random.default_rng(61), count=6, tol=TOL["fp32"])
+            t0 += time.perf_counter()
         cum.cum_free(ctx)
         del X
     el = time.perf_counter() - t0
@@ -416,6 +425,9 @@ def run_nu4_study(runs=100, n=100, t=1_000_000, tup=25_000, windows=61):
                         "Gaussian marginals; d=4 b=4 fp32" % (n, t, tup, windows),
             "runs": runs, "seconds": el, "first_run": curve,
             "nu4_quantiles_5_50_95": {"window_1": q(nu_first), "window_%d" % windows: q(nu_last)},
+            # the Gaussian window's expected nu_4: sqrt of the closed-form
+            # E||C_4||^2 of Gaussian sampling noise over ||Sigma||_F^2
+            "nu4_window_1_gaussian_noise_floor": math.sqrt(gaussian_noise_floor(S, t, 4)) / float(np.sum(S * S)),
             "paper_nu4_quantiles_5_50_95": {"gaussian": [0.004, 0.006, 0.011], "t_copula": [0.199, 0.209, 0.220]}}
 
 

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcum.so")
-SOURCES = ["api.cpp", "tables.cpp", "kernels.hip", "adjoint.hip", "noalloc.hip"]
+SOURCES = ["api.cpp", "tables.cpp", "kernels.hip", "combine_split.hip", "adjoint.hip", "noalloc.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # keep the compiler from emitting packed FP32 vector instructions

@@ -188,12 +188,15 @@ hipEvent_t pooled_event(cum_ctx* c) {
 }
 
 // Brackets one launch with HIP events when its class (0 = update,
-// 1 = combine, 2 = norms) is being profiled.
+// 1 = combine, 2 = norms) is being profiled.  With `own` the launch takes
+// the events itself (start() / stop()) and they carry the kernel's own
+// dispatch timestamps; otherwise they are recorded on the stream around it.
 struct Timed {
   cum_ctx* c;
   int cls;
+  bool own;
   hipEvent_t a = nullptr, b = nullptr;
-  Timed(cum_ctx* ctx, int k) : c(ctx), cls(k) {
+  Timed(cum_ctx* ctx, int k, bool own_events = false) : c(ctx), cls(k), own(own_events) {
     if (!(c->profile_mask & (1 << cls)) || c->no_events) return;
     if (c->profile_seen[cls]++ % c->profile_every != 0) return;
     a = pooled_event(c);
@@ -204,13 +207,23 @@ struct Timed {
       a = b = nullptr;
       return;
     }
-    (void)hipEventRecord(a, c->stream);
+    if (!own) (void)hipEventRecord(a, c->stream);
   }
+  hipEvent_t start() const { return a; }
+  hipEvent_t stop() const { return b; }
+  // With `own`: the launch went in and took the events.
+  void launched() { taken = true; }
   ~Timed() {
     if (!a) return;
-    (void)hipEventRecord(b, c->stream);
+    if (own && !taken) {  // the launch failed: the events were never recorded
+      c->event_pool.push_back(a);
+      c->event_pool.push_back(b);
+      return;
+    }
+    if (!own) (void)hipEventRecord(b, c->stream);
     c->events.push_back({cls, a, b});
   }
+  bool taken = false;
 };
 
 // Update tile shape: CUM_TILE=<TM>x<TN> overrides the default 2x2.
@@ -268,8 +281,9 @@ int run_contraction(cum_ctx* c, const char* xp, int64_t np, const char* xm, int6
       a.na = c->pending_na;
       c->norms_pending = false;
     }
-    Timed tm(c, 0);
-    CUM_TRY(launch_update(c->prec, c->tm, c->tn, c->d, a, c->nitems, c->stream));
+    Timed tm(c, 0, true);
+    CUM_TRY(launch_update(c->prec, c->tm, c->tn, c->d, a, c->nitems, c->stream, tm.start(), tm.stop()));
+    tm.launched();
   }
   return CUM_OK;
 }
@@ -320,7 +334,10 @@ int run_combine_and_norms(cum_ctx* c) {
     a.partial = c->partial[s];
     a.rec = c->combine == CUM_COMBINE_RECURSION;
     Timed tm(c, 1);
-    CUM_TRY(launch_combine(c->prec, s, a, c->T.ord[s].nblocks, c->stream));
+    if (combine_split_supported(s, c->b))
+      CUM_TRY(launch_combine_split(c->prec, s, a, c->T.ord[s].nblocks, c->stream));
+    else
+      CUM_TRY(launch_combine(c->prec, s, a, c->T.ord[s].nblocks, c->stream));
   }
   NormArgs na{};
   na.d = c->d;

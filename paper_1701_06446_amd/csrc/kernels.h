@@ -103,8 +103,14 @@ bool update_quad_supported(int prec, int n);
 int update_lds_stride(int n);
 // Rows per LDS chunk for a precision and stride (0: not supported).
 int update_chunk_rows(int prec, int str);
-hipError_t launch_update(int prec, int tm, int tn, int kmax, const UpdArgs& a, int nitems, hipStream_t st);
+// e0/e1 (null: none) record the update kernel's own start and end.
+hipError_t launch_update(int prec, int tm, int tn, int kmax, const UpdArgs& a, int nitems, hipStream_t st,
+                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_combine(int prec, int s, const CombArgs& a, int64_t nblocks, hipStream_t st);
+// The same per-order combine with every operand in LDS, the partition sum
+// grouped on the part holding the first position (orders 5 and 6, b = 4).
+bool combine_split_supported(int s, int b);
+hipError_t launch_combine_split(int prec, int s, const CombArgs& a, int64_t nblocks, hipStream_t st);
 hipError_t launch_norms(const NormArgs& a, hipStream_t st);
 // recursion: c_I = m_I - sum over B containing I's first position of c_B m_{I\B}
 // (2^(s-1) - 1 terms) instead of the partition sum of Alg. 4 (B(s) - 1 terms)

@@ -9,6 +9,7 @@
 //             {1..s} into 2..s parts of the product of lower-order cumulants at
 //             the sub-multi-indices, in FP64, one workgroup per stored block.
 //  k_norms    Alg. 5 (exponent 2) and Eq. (mef), deterministic fixed-order sums.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <hip/hip_vector_types.h>
 
@@ -1813,20 +1814,21 @@ hipError_t launch_update_batch(int prec, int str, bool vl, int kmax, const UpdAr
   }
 }
 
+// e0/e1 (may be null) take the kernel's own start and end timestamps.
 template <int P, int STR, bool VL>
-static void launch_kmax(int kmax, const UpdArgs& a, int nitems, hipStream_t st) {
+static void launch_kmax(int kmax, const UpdArgs& a, int nitems, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if constexpr (VL && QuadGeom<P, STR>::OK) {
     if (a.quad) {
       // a.items holds nitems rounded up to whole groups of four
       const dim3 grid((unsigned)((nitems + 3) / 4 + (a.with_norms ? 1 : 0)));
-      if (kmax <= 4) hipLaunchKernelGGL((k_update_quad<P, STR, 4>), grid, dim3(1024), 0, st, a);
-      else hipLaunchKernelGGL((k_update_quad<P, STR, 6>), grid, dim3(1024), 0, st, a);
+      if (kmax <= 4) hipExtLaunchKernelGGL((k_update_quad<P, STR, 4>), grid, dim3(1024), 0, st, e0, e1, 0, a);
+      else hipExtLaunchKernelGGL((k_update_quad<P, STR, 6>), grid, dim3(1024), 0, st, e0, e1, 0, a);
       return;
     }
   }
   const dim3 grid((unsigned)(nitems + (a.with_norms ? 1 : 0)));
-  if (kmax <= 4) hipLaunchKernelGGL((k_update<P, 2, 2, STR, VL, 4>), grid, dim3(256), 0, st, a);
-  else hipLaunchKernelGGL((k_update<P, 2, 2, STR, VL, 6>), grid, dim3(256), 0, st, a);
+  if (kmax <= 4) hipExtLaunchKernelGGL((k_update<P, 2, 2, STR, VL, 4>), grid, dim3(256), 0, st, e0, e1, 0, a);
+  else hipExtLaunchKernelGGL((k_update<P, 2, 2, STR, VL, 6>), grid, dim3(256), 0, st, e0, e1, 0, a);
 }
 
 // Whether launch_update takes the four-tiles-per-workgroup kernel for this
@@ -1850,10 +1852,11 @@ bool update_quad_supported(int prec, int n) {
 }
 
 template <int P, int STR>
-static hipError_t launch_one(int kmax, const UpdArgs& a, int nitems, hipStream_t st) {
+static hipError_t launch_one(int kmax, const UpdArgs& a, int nitems, hipStream_t st, hipEvent_t e0,
+                             hipEvent_t e1) {
   if constexpr (ChunkGeom<P, STR>::R >= ChunkGeom<P, STR>::UB) {
-    if (a.vec) launch_kmax<P, STR, true>(kmax, a, nitems, st);
-    else launch_kmax<P, STR, false>(kmax, a, nitems, st);
+    if (a.vec) launch_kmax<P, STR, true>(kmax, a, nitems, st, e0, e1);
+    else launch_kmax<P, STR, false>(kmax, a, nitems, st, e0, e1);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -1861,12 +1864,13 @@ static hipError_t launch_one(int kmax, const UpdArgs& a, int nitems, hipStream_t
 }
 
 template <int P>
-static hipError_t launch_update_p(int str, int kmax, const UpdArgs& a, int nitems, hipStream_t st) {
+static hipError_t launch_update_p(int str, int kmax, const UpdArgs& a, int nitems, hipStream_t st, hipEvent_t e0,
+                                  hipEvent_t e1) {
   switch (str) {
-    case 36: return launch_one<P, 36>(kmax, a, nitems, st);
-    case 68: return launch_one<P, 68>(kmax, a, nitems, st);
-    case 132: return launch_one<P, 132>(kmax, a, nitems, st);
-    case 260: return launch_one<P, 260>(kmax, a, nitems, st);
+    case 36: return launch_one<P, 36>(kmax, a, nitems, st, e0, e1);
+    case 68: return launch_one<P, 68>(kmax, a, nitems, st, e0, e1);
+    case 132: return launch_one<P, 132>(kmax, a, nitems, st, e0, e1);
+    case 260: return launch_one<P, 260>(kmax, a, nitems, st, e0, e1);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1892,14 +1896,15 @@ int update_chunk_rows(int prec, int str) {
   }
 }
 
-hipError_t launch_update(int prec, int tm, int tn, int kmax, const UpdArgs& a, int nitems, hipStream_t st) {
+hipError_t launch_update(int prec, int tm, int tn, int kmax, const UpdArgs& a, int nitems, hipStream_t st,
+                         hipEvent_t e0, hipEvent_t e1) {
   if (nitems <= 0) return hipSuccess;
   if (!update_tile_supported(tm, tn) || kmax < 1 || kmax > 6) return hipErrorInvalidValue;
   const int str = update_lds_stride(a.n);
   switch (prec) {
-    case PREC_F64: return launch_update_p<PREC_F64>(str, kmax, a, nitems, st);
-    case PREC_F32: return launch_update_p<PREC_F32>(str, kmax, a, nitems, st);
-    case PREC_BF16X3: return launch_update_p<PREC_BF16X3>(str, kmax, a, nitems, st);
+    case PREC_F64: return launch_update_p<PREC_F64>(str, kmax, a, nitems, st, e0, e1);
+    case PREC_F32: return launch_update_p<PREC_F32>(str, kmax, a, nitems, st, e0, e1);
+    case PREC_BF16X3: return launch_update_p<PREC_BF16X3>(str, kmax, a, nitems, st, e0, e1);
     default: return hipErrorInvalidValue;
   }
 }
