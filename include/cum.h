@@ -283,12 +283,13 @@ int cum_batch_free(cum_batch *batch);
  * memory owned by the caller.  w holds d+1 host doubles (w[0] unused).
  * Forward: FP32 moment contraction, FP64 combine (Alg. 3/4) and norms
  * (Alg. 5); reverse: FP64 (Alg. 4 backwards, then the derivative of
- * Eq. (mom)), with FP64 atomic additions in the reverse combine (results
- * reproducible up to their order).  L (host) receives the loss.
+ * Eq. (mom), the latter on FP64 matrix cores).  Every sum is taken in a
+ * fixed order (no atomics): repeated calls on the same inputs return
+ * bitwise equal results.  L (host) receives the loss.
  * Synchronises `hip_stream`; allocates and frees its own temporaries.
  * CUM_ESIZE when n > 64, when orders 1..d hold more than 2^24 stored
- * elements, or when the reverse combine's LDS would exceed 64 KB
- * ((b+1)^s - 1 - b^s > 4096 for some s <= d).
+ * elements, or when a block's moment lattice does not fit the reverse
+ * combine's LDS ((b+1)^s - 1 > 19200 for some s <= d).
  */
 int cum_loss_grad(int n, int d, int b, const float *X, int64_t t, const float *W, const double *w,
                   double *L, float *dX, float *dW, void *hip_stream);

@@ -7,9 +7,9 @@ csrc headers are unchanged since it was made.
 """
 from __future__ import annotations
 
-import glob
 import hashlib
 import os
+import re
 import subprocess
 import sys
 from concurrent.futures import ThreadPoolExecutor
@@ -31,9 +31,23 @@ def _clean(text: str) -> str:
     return "\n".join(l for l in text.splitlines() if "packed-fp32-ops" not in l and l.strip())
 
 
+def _includes(path: str, seen: set) -> None:
+    """The project headers `path` includes, directly or not (quoted includes)."""
+    with open(path) as f:
+        for line in f:
+            m = re.match(r'\s*#\s*include\s+"([^"]+)"', line)
+            if m:
+                inc = os.path.normpath(os.path.join(os.path.dirname(path), m.group(1)))
+                if os.path.exists(inc) and inc not in seen:
+                    seen.add(inc)
+                    _includes(inc, seen)
+
+
 def _digest(src: str) -> str:
     h = hashlib.sha256(" ".join(FLAGS).encode())
-    for p in [src] + sorted(glob.glob(os.path.join(CSRC, "*.h"))) + [os.path.join(HERE, "..", "include", "cum.h")]:
+    deps = set()
+    _includes(src, deps)
+    for p in [src] + sorted(deps):
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:20]

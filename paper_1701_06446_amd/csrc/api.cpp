@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <new>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/cum.h"
@@ -65,6 +66,17 @@ struct cum_ctx {
   // tiles (M = N = 0)
   bool quad = false;
   UpdItem* qitems = nullptr;
+  std::vector<UpdItem> h_qitems;
+  // split contraction (init and recalculation of contexts with few tiles):
+  // room for split_cap chunks' copies of the running sums, their argument
+  // blocks, and the quad items repeated per chunk (ctx = chunk)
+  int split_cap = 0;
+  void* split_state = nullptr;
+  UpdArgs* d_split_args = nullptr;
+  UpdItem* d_split_items = nullptr;
+  int split_args_cap = 0;
+  std::vector<UpdArgs> h_split_args;
+  std::vector<UpdArgs> h_split_prev;  // the blocks on the device
   // FIFO mode (fifo_p > 0): fifo_q = t / fifo_p slots of batch increments
   // per order, slot fifo_head holding the oldest batch of the window
   int64_t fifo_p = 0;
@@ -170,6 +182,14 @@ void release(cum_ctx* c) {
   c->owned.clear();
   if (c->stage) (void)hipFree(c->stage);
   c->stage = nullptr;
+  if (c->split_state) (void)hipFree(c->split_state);
+  if (c->d_split_args) (void)hipFree(c->d_split_args);
+  if (c->d_split_items) (void)hipFree(c->d_split_items);
+  c->split_state = nullptr;
+  c->d_split_args = nullptr;
+  c->d_split_items = nullptr;
+  c->split_cap = 0;
+  c->split_args_cap = 0;
 }
 
 int check_shape(int n, int d, int b) {
@@ -259,8 +279,149 @@ void set_fifo(const cum_ctx* c, UpdArgs& a, int mode, int slot) {
     a.snap[k] = mode ? (char*)c->snap[k] + (size_t)slot * (size_t)c->T.ord[k].nelems * c->st_size : nullptr;
 }
 
+int flush_norms(cum_ctx* c);
+
+int64_t state_elems(const cum_ctx* c) {
+  int64_t tot = 0;
+  for (int k = 1; k <= c->d; ++k) tot += c->T.ord[k].nelems;
+  return tot;
+}
+
+// Room for `nsplit` chunks' state copies and `nargs` argument blocks of a
+// split contraction (grown on demand).
+int ensure_split(cum_ctx* c, int nsplit, int nargs) {
+  if (nsplit > c->split_cap) {
+    if (c->split_state) (void)hipFree(c->split_state);
+    if (c->d_split_items) (void)hipFree(c->d_split_items);
+    c->split_state = nullptr;
+    c->d_split_items = nullptr;
+    c->split_cap = 0;
+    const size_t sbytes = (size_t)nsplit * 2 * (size_t)state_elems(c) * c->st_size;
+    const size_t nq = c->h_qitems.size();
+    std::vector<UpdItem> rep((size_t)nsplit * nq);
+    for (int s = 0; s < nsplit; ++s)
+      for (size_t i = 0; i < nq; ++i) {
+        rep[(size_t)s * nq + i] = c->h_qitems[i];
+        rep[(size_t)s * nq + i].ctx = s;
+      }
+    if (hipMalloc(&c->split_state, sbytes) != hipSuccess ||
+        hipMalloc((void**)&c->d_split_items, rep.size() * sizeof(UpdItem)) != hipSuccess) {
+      (void)hipGetLastError();
+      return CUM_ENOMEM;
+    }
+    CUM_TRY(hipMemcpy(c->d_split_items, rep.data(), rep.size() * sizeof(UpdItem), hipMemcpyHostToDevice));
+    // zero once: every fold leaves the copies it read zeroed again
+    CUM_TRY(hipMemset(c->split_state, 0, sbytes));
+    c->split_cap = nsplit;
+  }
+  if (nargs > c->split_args_cap) {
+    if (c->d_split_args) (void)hipFree(c->d_split_args);
+    c->d_split_args = nullptr;
+    c->split_args_cap = 0;
+    if (hipMalloc((void**)&c->d_split_args, (size_t)nargs * sizeof(UpdArgs)) != hipSuccess) {
+      (void)hipGetLastError();
+      return CUM_ENOMEM;
+    }
+    c->split_args_cap = nargs;
+    c->h_split_prev.clear();
+  }
+  return CUM_OK;
+}
+
+// Chunks of a plus-rows-only contraction in one launch when the context has
+// too few tiles to fill the device chunk by chunk (see FoldArgs).  Chunks
+// are at most kRowChunk rows, fewer (multiples of 256) when the tiles are
+// so few that kRowChunk-row chunks would still leave the device idle.
+constexpr int64_t kSplitWorkgroups = 512;                 // target workgroups per launch
+constexpr int64_t kSplitMaxBytes = (int64_t)256 << 20;    // cap of the chunks' state copies
+
+bool split_eligible(const cum_ctx* c, const char* xp, int64_t np, const char* xm, int64_t nm, int fifo) {
+  (void)xm;
+  return fifo == 0 && nm == 0 && np > 256 && c->quad && !c->no_events && (c->n * c->x_size) % 16 == 0 &&
+         (uintptr_t)xp % 16 == 0 && (int64_t)c->h_qitems.size() / 4 * 2 < kSplitWorkgroups;
+}
+
+int64_t split_chunk_rows(const cum_ctx* c, int64_t np) {
+  const int64_t nq = (int64_t)c->h_qitems.size() / 4;
+  const int64_t want = (np * nq + kSplitWorkgroups - 1) / kSplitWorkgroups;
+  return std::max<int64_t>(256, std::min<int64_t>(kRowChunk, (want + 255) / 256 * 256));
+}
+
+// fresh: the running sums are zero before this contraction (they are
+// written, not read)
+int run_contraction_split(cum_ctx* c, const char* xp, int64_t np, bool fresh) {
+  const int64_t nq = (int64_t)c->h_qitems.size() / 4;
+  const int64_t rows = split_chunk_rows(c, np);
+  const int64_t nchunks = (np + rows - 1) / rows;
+  const int64_t per = std::max<int64_t>(1, std::min<int64_t>(nchunks, (kSplitWorkgroups + nq - 1) / nq));
+  const int64_t tot = state_elems(c);
+  const int group = (int)std::min<int64_t>(per, std::max<int64_t>(1, kSplitMaxBytes / (2 * tot * (int64_t)c->st_size)));
+  if (int rc = ensure_split(c, group, (int)nchunks)) return rc;
+  if (c->norms_pending)
+    if (int rc = flush_norms(c)) return rc;
+  const size_t rb = (size_t)c->n * c->x_size;
+  const int str = update_lds_stride(c->n);
+  FoldArgs fa{};
+  fa.d = c->d;
+  fa.tot = tot;
+  int64_t o = 0;
+  for (int k = 1; k <= c->d; ++k) {
+    fa.off[k] = o;
+    o += c->T.ord[k].nelems;
+    fa.s_hi[k] = c->s_hi[k];
+    fa.s_lo[k] = c->s_lo[k];
+  }
+  fa.off[c->d + 1] = tot;
+  fa.split = c->split_state;
+  // every chunk's argument block (chunk i of a group uses state copy i mod group)
+  c->h_split_args.resize((size_t)nchunks);
+  for (int64_t ci = 0; ci < nchunks; ++ci) {
+    const int64_t q0 = ci * rows;
+    UpdArgs a = base_args(c);
+    set_fifo(c, a, 0, 0);
+    a.xp = xp + (size_t)q0 * rb;
+    a.np = (int)std::min<int64_t>(rows, np - q0);
+    a.xm = nullptr;
+    a.nm = 0;
+    a.vec = 1;
+    a.quad = 1;
+    a.items = nullptr;
+    a.with_norms = 0;
+    char* base = (char*)c->split_state + (size_t)(ci % group) * 2 * (size_t)tot * c->st_size;
+    for (int k = 1; k <= c->d; ++k) {
+      a.s_hi[k] = base + (size_t)fa.off[k] * c->st_size;
+      a.s_lo[k] = base + (size_t)(tot + fa.off[k]) * c->st_size;
+    }
+    c->h_split_args[(size_t)ci] = a;
+  }
+  // uploaded only when they changed: a repeated recalculation of the same
+  // buffer (as inside a captured graph) reuses the blocks on the device
+  if (c->h_split_prev.size() != c->h_split_args.size() ||
+      memcmp(c->h_split_prev.data(), c->h_split_args.data(), c->h_split_args.size() * sizeof(UpdArgs)) != 0) {
+    CUM_TRY(hipMemcpyAsync(c->d_split_args, c->h_split_args.data(), c->h_split_args.size() * sizeof(UpdArgs),
+                           hipMemcpyHostToDevice, c->stream));
+    CUM_TRY(hipStreamSynchronize(c->stream));  // the host blocks may change on the next call
+    c->h_split_prev = c->h_split_args;
+  }
+  for (int64_t g0 = 0; g0 < nchunks; g0 += group) {
+    const int ns = (int)std::min<int64_t>(group, nchunks - g0);
+    {
+      Timed tm(c, 0);
+      CUM_TRY(launch_update_quad_batch(c->prec, str, c->d, c->d_split_args + g0, c->d_split_items,
+                                       (int)((int64_t)ns * nq * 4), (int)((int64_t)ns * nq), c->stream));
+    }
+    fa.nsplit = ns;
+    fa.fresh = (fresh && g0 == 0) ? 1 : 0;
+    CUM_TRY(launch_fold_splits(c->prec, fa, c->stream));
+  }
+  return CUM_OK;
+}
+
+// allow_split: a context with few tiles may contract a long plus-only run
+// of rows chunk-parallel; fresh: the running sums are zero beforehand
 int run_contraction(cum_ctx* c, const char* xp, int64_t np, const char* xm, int64_t nm, int fifo = 0,
-                    int slot = 0) {
+                    int slot = 0, bool allow_split = false, bool fresh = false) {
+  if (allow_split && split_eligible(c, xp, np, xm, nm, fifo)) return run_contraction_split(c, xp, np, fresh);
   UpdArgs a = base_args(c);
   set_fifo(c, a, fifo, slot);
   const int64_t rows = np > nm ? np : nm;
@@ -515,8 +676,8 @@ int init_ctx(cum_ctx** out, int n, int d, int b, const void* X, int64_t t, int64
   if ((e = upload(c, &c->items, items, &used)) != hipSuccess) return fail(e);
   c->quad = update_quad_supported(prec, n) && !items.empty();
   if (c->quad) {
-    const std::vector<UpdItem> q = pack_quads(items);
-    if ((e = upload(c, &c->qitems, q, &used)) != hipSuccess) return fail(e);
+    c->h_qitems = pack_quads(items);
+    if ((e = upload(c, &c->qitems, c->h_qitems, &used)) != hipSuccess) return fail(e);
   }
   if ((e = dalloc(c, (void**)&c->norms, (size_t)2 * (d + 1) * 8, &used)) != hipSuccess) return fail(e);
   if ((e = dalloc(c, &c->zero, UPD_ZERO_BYTES, &used)) != hipSuccess) return fail(e);
@@ -562,7 +723,7 @@ int init_ctx(cum_ctx** out, int n, int d, int b, const void* X, int64_t t, int64
     for (int q = 0; q < c->fifo_q && rc == CUM_OK; ++q)
       rc = run_contraction(c, xw + (size_t)q * bb, fifo_p, nullptr, 0, 1, q);
   } else {
-    rc = run_contraction(c, xw, t, nullptr, 0);
+    rc = run_contraction(c, xw, t, nullptr, 0, 0, 0, true, true);  // the sums were just zeroed
   }
   if (rc == CUM_OK) rc = run_combine_and_norms(c);
   if (rc == CUM_OK && (e = hipStreamSynchronize(c->stream)) != hipSuccess) {
@@ -696,10 +857,18 @@ int cum_recompute(cum_ctx* c, const void* X) {
     CUM_TRY(hipStreamWaitEvent(c->stream, c->batch_done, 0));
     c->direct_since_batch = true;
   }
-  for (int k = 1; k <= c->d; ++k) {
-    const size_t bytes = (size_t)c->T.ord[k].nelems * c->st_size;
-    CUM_TRY(hipMemsetAsync(c->s_hi[k], 0, bytes, c->stream));
-    CUM_TRY(hipMemsetAsync(c->s_lo[k], 0, bytes, c->stream));
+  // the chunk-parallel contraction writes the running sums outright
+  const bool split = !c->fifo_q && split_eligible(c, xw, c->t, nullptr, 0, 0);
+  if (!split) {
+    ZeroArgs za{};
+    for (int k = 1; k <= c->d; ++k) {
+      const int64_t words = c->T.ord[k].nelems * (int64_t)c->st_size / 4;
+      za.ptr[za.count] = c->s_hi[k];
+      za.words[za.count++] = words;
+      za.ptr[za.count] = c->s_lo[k];
+      za.words[za.count++] = words;
+    }
+    CUM_TRY(launch_zero(za, c->stream));
   }
   int rc = CUM_OK;
   if (c->fifo_q) {
@@ -708,7 +877,7 @@ int cum_recompute(cum_ctx* c, const void* X) {
       rc = run_contraction(c, xw + (size_t)q * bb, c->fifo_p, nullptr, 0, 1, q);
     c->fifo_head = 0;
   } else {
-    rc = run_contraction(c, xw, c->t, nullptr, 0);
+    rc = run_contraction(c, xw, c->t, nullptr, 0, 0, 0, true, split);
   }
   if (rc != CUM_OK) return rc;
   rc = run_combine_and_norms(c);
@@ -1172,6 +1341,128 @@ void build_ybar_items(const Tables& T, int groups, std::vector<int32_t>& items, 
   }
 }
 
+// Reverse-combine gather lists of order s: for every block of the lower
+// orders 1 .. s-1 (concatenated by order, bstart[q] = first block of order
+// q), the (order-s block << 6 | mask) pairs whose sub-tuple is that block,
+// in increasing (block, mask) order.
+int build_rev_lists(const Tables& T, int s, std::vector<int64_t>& bstart, std::vector<int32_t>& ptr,
+                    std::vector<int32_t>& ent) {
+  const int nm = 1 << s;
+  bstart.assign((size_t)s + 1, 0);
+  int64_t nlow = 0;
+  for (int q = 1; q < s; ++q) {
+    bstart[(size_t)q] = nlow;
+    nlow += T.ord[q].nblocks;
+  }
+  bstart[(size_t)s] = nlow;
+  const int64_t nb = T.ord[s].nblocks;
+  if (nb >= ((int64_t)1 << 25) || nb * (nm - 2) >= ((int64_t)1 << 31)) return CUM_ESIZE;
+  std::vector<int64_t> cnt((size_t)nlow + 1, 0);
+  for (int64_t r = 0; r < nb; ++r)
+    for (int m = 1; m < nm - 1; ++m) {
+      const int q = __builtin_popcount((unsigned)m);
+      cnt[(size_t)(bstart[(size_t)q] + T.subrank[s][(size_t)r * nm + m] + 1)] += 1;
+    }
+  ptr.assign((size_t)nlow + 1, 0);
+  for (int64_t i = 0; i < nlow; ++i) ptr[(size_t)i + 1] = (int32_t)(ptr[(size_t)i] + cnt[(size_t)i + 1]);
+  ent.assign((size_t)ptr[(size_t)nlow], 0);
+  std::vector<int32_t> pos(ptr.begin(), ptr.end() - 1);
+  for (int64_t r = 0; r < nb; ++r)
+    for (int m = 1; m < nm - 1; ++m) {
+      const int q = __builtin_popcount((unsigned)m);
+      const size_t at = (size_t)(bstart[(size_t)q] + T.subrank[s][(size_t)r * nm + m]);
+      ent[(size_t)pos[at]++] = (int32_t)((r << 6) | m);
+    }
+  return CUM_OK;
+}
+
+// Tables of Y_bar = P G.  Rows of G: the sorted tuples J of orders 0 .. d-1
+// over the n columns, in increasing order and lexicographic within an order
+// (kpad rows, padded with empty rows); facs[row] holds J's columns, one per
+// byte, then the index n (which reads 1).  Entry lists of G[row, j]: every
+// stored element e (of the concatenated pyramids, offsets `base`) whose
+// multi-index is J plus j, with the number of positions of e holding j.
+int build_g_tables(const Tables& T, int n, int d, int64_t splits_max, const int64_t* base, int ncol,
+                   int& splits, int64_t& kpad, std::vector<uint64_t>& facs, std::vector<int64_t>& gptr,
+                   std::vector<int64_t>& gent, int64_t t) {
+  std::unordered_map<uint64_t, int64_t> rowof;
+  std::vector<std::vector<int>> rows;
+  auto key = [](const int* J, int len) {
+    uint64_t k = (uint64_t)len;
+    for (int q = 0; q < len; ++q) k |= (uint64_t)(J[q] + 1) << (3 + 7 * q);
+    return k;
+  };
+  for (int len = 0; len < d; ++len) {
+    std::vector<int> J((size_t)len, 0);
+    while (true) {
+      rowof[key(J.data(), len)] = (int64_t)rows.size();
+      rows.push_back(J);
+      int q = len - 1;
+      while (q >= 0 && J[(size_t)q] == n - 1) --q;
+      if (q < 0) break;
+      ++J[(size_t)q];
+      for (int r = q + 1; r < len; ++r) J[(size_t)r] = J[(size_t)q];
+    }
+  }
+  const int64_t K = (int64_t)rows.size();
+  const int64_t tiles = (t + 127) / 128;  // row tiles of the Y_bar kernel
+  splits = (int)std::max<int64_t>(1, std::min<int64_t>(splits_max, (1024 + tiles - 1) / tiles));
+  kpad = (K + 16 * splits - 1) / (16 * splits) * (16 * splits);
+  if (kpad * ncol > ((int64_t)1 << 24)) return CUM_ESIZE;
+  facs.assign((size_t)kpad, 0);
+  for (int64_t r = 0; r < kpad; ++r) {
+    uint64_t f = 0;
+    for (int q = 0; q < 8; ++q) {
+      const int v = (r < K && q < (int)rows[(size_t)r].size()) ? rows[(size_t)r][(size_t)q] : n;
+      f |= (uint64_t)v << (8 * q);
+    }
+    facs[(size_t)r] = f;
+  }
+  std::vector<std::pair<int64_t, int64_t>> pairs;  // (G index, element offset)
+  int64_t total = 0;
+  for (int k = 1; k <= d; ++k) total += T.ord[k].nelems * k;
+  if (total > ((int64_t)1 << 26)) return CUM_ESIZE;
+  pairs.reserve((size_t)total);
+  int idx[CUM_MAXD], J[CUM_MAXD];
+  for (int k = 1; k <= d; ++k) {
+    const OrderInfo& o = T.ord[k];
+    for (int64_t blk = 0; blk < o.nblocks; ++blk)
+      for (int64_t l = 0; l < o.bk; ++l) {
+        int64_t rem = l;
+        bool pad = false;
+        for (int q = k - 1; q >= 0; --q) {
+          idx[q] = T.tuples[k][(size_t)blk * k + q] * T.b + (int)(rem % T.b);
+          rem /= T.b;
+          pad = pad || idx[q] >= n;
+        }
+        if (pad) continue;
+        const int64_t off = base[k] + blk * o.bk + l;
+        for (int q = 0; q < k; ++q) {
+          int len = 0;
+          for (int u = 0; u < k; ++u)
+            if (u != q) J[len++] = idx[u];
+          std::sort(J, J + len);
+          const int64_t row = rowof.at(key(J, len));
+          pairs.emplace_back(row * ncol + idx[q], off);
+        }
+      }
+  }
+  std::sort(pairs.begin(), pairs.end());
+  gptr.assign((size_t)(kpad * ncol) + 1, 0);
+  gent.clear();
+  size_t i = 0;
+  for (int64_t r = 0; r < kpad * ncol; ++r) {
+    while (i < pairs.size() && pairs[i].first == r) {
+      size_t j = i;
+      while (j < pairs.size() && pairs[j] == pairs[i]) ++j;
+      gent.push_back(pairs[i].second | ((int64_t)(j - i) << 48));
+      i = j;
+    }
+    gptr[(size_t)r + 1] = (int64_t)gent.size();
+  }
+  return CUM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1179,24 +1470,56 @@ extern "C" {
 struct cum_loss_plan {
   int n = 0, d = 0, b = 0;
   int64_t t = 0;
-  hipStream_t st = nullptr;
+  hipStream_t caller = nullptr;  // the stream the caller's X and W are ordered on
+  hipStream_t st = nullptr;      // the plan's own stream (the pass is captured on it)
+  hipEvent_t ev = nullptr;
+  hipGraphExec_t graph = nullptr;
+  bool eager_only = false;       // capture failed: every call runs the pass eagerly
   cum_ctx* c = nullptr;  // FP32 context over Y = X W^T
   float* Y = nullptr;
-  double* Cbar[CUM_MAXD + 1] = {};
+  // plan-owned copies of the inputs and outputs (the captured pass reads and
+  // writes only these), the weights on the device and in pinned host memory,
+  // and the norms read back
+  float* Xp = nullptr;
+  float* Wp = nullptr;
+  float* dXp = nullptr;
+  float* dWp = nullptr;
+  double* d_w = nullptr;
+  double* h_w = nullptr;
+  double* h_norms = nullptr;
+  double* Cbar[CUM_MAXD + 1] = {};  // views into one allocation, orders concatenated
+  int64_t cbar_base[CUM_MAXD + 1] = {};
+  // reverse combine
+  double* rev_part = nullptr;
+  RevCollectArgs rc[CUM_MAXD + 1] = {};
+  int64_t rc_nblocks[CUM_MAXD + 1] = {};
+  // Y_bar on matrix cores (mma) or block by block
+  bool mma = false;
+  int splits = 1, ncol = 16, F = 1;
+  int64_t kpad = 0;
+  uint64_t* facs = nullptr;
+  double* G = nullptr;
+  int64_t* gptr = nullptr;
+  int64_t* gent = nullptr;
   uint8_t* tuples[CUM_MAXD + 1] = {};
   int32_t* items = nullptr;
-  int32_t* gptr = nullptr;
+  int32_t* bgptr = nullptr;
   int groups = 1;
-  double* part = nullptr;
-  double* Ybar = nullptr;
+  double* part = nullptr;    // splits (or groups) x t x n
+  double* dwpart = nullptr;  // row tiles x n x n
   std::vector<void*> owned;
 };
 
 int cum_loss_plan_free(cum_loss_plan* pl) {
   if (!pl) return CUM_OK;
-  if (pl->st || pl->c) (void)hipStreamSynchronize(pl->st);
+  if (pl->st) (void)hipStreamSynchronize(pl->st);
+  if (pl->graph) (void)hipGraphExecDestroy(pl->graph);
   if (pl->c) cum_free(pl->c);
   for (void* p : pl->owned) (void)hipFree(p);
+  if (pl->h_w) (void)hipHostFree(pl->h_w);
+  if (pl->h_norms) (void)hipHostFree(pl->h_norms);
+  if (pl->ev) (void)hipEventDestroy(pl->ev);
+  if (pl->st) (void)hipStreamDestroy(pl->st);
   delete pl;
   return CUM_OK;
 }
@@ -1210,11 +1533,11 @@ int cum_loss_plan_create(cum_loss_plan** out, int n, int d, int b, int64_t t, vo
   // Y_bar stages 256 rows of Y (256 n floats) in LDS; the host table of
   // (element, column) pairs holds up to d entries per stored element
   if (n > 64) return CUM_ESIZE;
-  // the reverse combine keeps staged cumulants and their gradients in LDS
+  // the reverse combine stages a block's moment lattice and gradients in LDS
   for (int s = 2; s <= d; ++s) {
-    int64_t tot = 1, bs = 1;
-    for (int q = 0; q < s; ++q) { tot *= (b + 1); bs *= b; }
-    if ((tot - 1 - bs) * 2 * (int64_t)sizeof(double) > 65536) return CUM_ESIZE;
+    int64_t tot = 1;
+    for (int q = 0; q < s; ++q) tot *= (b + 1);
+    if (tot - 1 > REV_LDS_DOUBLES) return CUM_ESIZE;
   }
   {
     Tables probe;
@@ -1226,7 +1549,7 @@ int cum_loss_plan_create(cum_loss_plan** out, int n, int d, int b, int64_t t, vo
   cum_loss_plan* pl = new (std::nothrow) cum_loss_plan();
   if (!pl) return CUM_ENOMEM;
   pl->n = n; pl->d = d; pl->b = b; pl->t = t;
-  pl->st = (hipStream_t)hip_stream;
+  pl->caller = (hipStream_t)hip_stream;
   auto fail = [&](int r) {
     cum_loss_plan_free(pl);
     return r;
@@ -1238,93 +1561,265 @@ int cum_loss_plan_create(cum_loss_plan** out, int n, int d, int b, int64_t t, vo
     return e;
   };
   hipError_t e;
+  if ((e = hipStreamCreateWithFlags(&pl->st, hipStreamNonBlocking)) != hipSuccess) {
+    pl->st = nullptr;
+    return fail(map_err(e));
+  }
+  if ((e = hipEventCreateWithFlags(&pl->ev, hipEventDisableTiming)) != hipSuccess) {
+    pl->ev = nullptr;
+    return fail(map_err(e));
+  }
+  if ((e = hipHostMalloc((void**)&pl->h_w, (size_t)(d + 1) * sizeof(double), hipHostMallocDefault)) != hipSuccess ||
+      (e = hipHostMalloc((void**)&pl->h_norms, (size_t)2 * (d + 1) * sizeof(double), hipHostMallocDefault)) !=
+          hipSuccess)
+    return fail(map_err(e));
+  if ((e = alloc((void**)&pl->Xp, (size_t)t * n * sizeof(float))) != hipSuccess ||
+      (e = alloc((void**)&pl->dXp, (size_t)t * n * sizeof(float))) != hipSuccess ||
+      (e = alloc((void**)&pl->Wp, (size_t)n * n * sizeof(float))) != hipSuccess ||
+      (e = alloc((void**)&pl->dWp, (size_t)n * n * sizeof(float))) != hipSuccess ||
+      (e = alloc((void**)&pl->d_w, (size_t)(d + 1) * sizeof(double))) != hipSuccess)
+    return fail(map_err(e));
   if ((e = alloc((void**)&pl->Y, (size_t)t * n * sizeof(float))) != hipSuccess) return fail(map_err(e));
   if ((e = hipMemsetAsync(pl->Y, 0, (size_t)t * n * sizeof(float), pl->st)) != hipSuccess) return fail(map_err(e));
   if ((e = hipStreamSynchronize(pl->st)) != hipSuccess) return fail(map_err(e));
-  rc = cum_init(&pl->c, n, d, b, pl->Y, t, CUM_FP32, hip_stream);
+  rc = cum_init(&pl->c, n, d, b, pl->Y, t, CUM_FP32, pl->st);
   if (rc != CUM_OK) return fail(rc);
-  for (int k = 1; k <= d; ++k)
-    if ((e = alloc((void**)&pl->Cbar[k], (size_t)pl->c->T.ord[k].nelems * sizeof(double))) != hipSuccess)
-      return fail(map_err(e));
-  // Y_bar: row tiles of 64 times block groups, enough workgroups to fill the
-  // device, partial sums capped at 256 MB
-  const int64_t tiles = (t + 63) / 64;
-  int groups = (int)std::max<int64_t>(1, std::min<int64_t>(64, (2048 + tiles - 1) / tiles));
-  while (groups > 1 && (int64_t)groups * t * n * 8 > ((int64_t)256 << 20)) --groups;
-  pl->groups = groups;
-  std::vector<int32_t> items, gptr;
-  build_ybar_items(pl->c->T, groups, items, gptr);
+  const Tables& T = pl->c->T;
+  int64_t ctot = 0;
+  for (int k = 1; k <= d; ++k) {
+    pl->cbar_base[k] = ctot;
+    ctot += T.ord[k].nelems;
+  }
+  double* cbar_all = nullptr;
+  if ((e = alloc((void**)&cbar_all, (size_t)ctot * sizeof(double))) != hipSuccess) return fail(map_err(e));
+  for (int k = 1; k <= d; ++k) pl->Cbar[k] = cbar_all + pl->cbar_base[k];
   auto up = [&](void** dst, const void* src, size_t bytes) {
     hipError_t r = alloc(dst, bytes);
     if (r == hipSuccess && bytes) r = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
     return r;
   };
-  for (int k = 1; k <= d; ++k)
-    if ((e = up((void**)&pl->tuples[k], pl->c->T.tuples[k].data(), pl->c->T.tuples[k].size())) != hipSuccess)
+  // reverse combine: partials of the largest order, gather lists per order
+  int64_t rev_max = 0;
+  for (int s = 2; s <= d; ++s) {
+    int64_t tot = 1, bs = 1;
+    for (int q = 0; q < s; ++q) { tot *= (b + 1); bs *= b; }
+    tot = tot - 1 - bs;
+    rev_max = std::max(rev_max, T.ord[s].nblocks * tot);
+    RevCollectArgs& ra = pl->rc[s];
+    ra.b = b;
+    ra.tot = (int)tot;
+    int off = 0;
+    for (int m = 1; m < (1 << s) - 1; ++m) {
+      ra.moff[m] = off;
+      int bl = 1;
+      for (int q = 0; q < __builtin_popcount((unsigned)m); ++q) bl *= b;
+      off += bl;
+    }
+    std::vector<int64_t> bstart;
+    std::vector<int32_t> ptr, ent;
+    if ((rc = build_rev_lists(T, s, bstart, ptr, ent)) != CUM_OK) return fail(rc);
+    int64_t es = 0;
+    for (int q = 1; q < s; ++q) {
+      ra.estart[q] = es;
+      ra.bstart[q] = bstart[(size_t)q];
+      ra.bk[q] = T.ord[q].bk;
+      es += T.ord[q].nelems;
+    }
+    ra.estart[s] = es;
+    ra.bstart[s] = bstart[(size_t)s];
+    pl->rc_nblocks[s] = bstart[(size_t)s];  // blocks of the lower orders
+    if ((e = up((void**)&ra.ptr, ptr.data(), ptr.size() * sizeof(int32_t))) != hipSuccess) return fail(map_err(e));
+    if ((e = up((void**)&ra.ent, ent.data(), ent.size() * sizeof(int32_t))) != hipSuccess) return fail(map_err(e));
+    for (int k = 1; k <= d; ++k) ra.Cbar[k] = pl->Cbar[k];
+  }
+  if ((e = alloc((void**)&pl->rev_part, (size_t)std::max<int64_t>(rev_max, 1) * sizeof(double))) != hipSuccess)
+    return fail(map_err(e));
+  for (int s = 2; s <= d; ++s) pl->rc[s].part = pl->rev_part;
+  // Y_bar: on matrix cores when its gathered matrix stays small, else block
+  // by block (row tiles of 64 times block groups, partials capped at 256 MB)
+  const int64_t tiles = (t + 63) / 64;
+  int nsplit = 1;
+  {
+    pl->ncol = (n + 15) / 16 * 16;
+    pl->F = d > 1 ? d - 1 : 1;
+    std::vector<uint64_t> facs;
+    std::vector<int64_t> gptr, gent;
+    int64_t cap = 1;
+    while (cap < 16 && (cap + 1) * t * n * 8 <= ((int64_t)256 << 20)) ++cap;
+    if (build_g_tables(T, n, d, cap, pl->cbar_base, pl->ncol, pl->splits, pl->kpad, facs, gptr, gent, t) ==
+        CUM_OK) {
+      pl->mma = true;
+      nsplit = pl->splits;
+      if ((e = up((void**)&pl->facs, facs.data(), facs.size() * sizeof(uint64_t))) != hipSuccess)
+        return fail(map_err(e));
+      if ((e = up((void**)&pl->gptr, gptr.data(), gptr.size() * sizeof(int64_t))) != hipSuccess)
+        return fail(map_err(e));
+      if ((e = up((void**)&pl->gent, gent.data(), std::max<size_t>(gent.size(), 1) * sizeof(int64_t))) !=
+          hipSuccess)
+        return fail(map_err(e));
+      if ((e = alloc((void**)&pl->G, (size_t)(pl->kpad * pl->ncol) * sizeof(double))) != hipSuccess)
+        return fail(map_err(e));
+    }
+  }
+  if (!pl->mma) {
+    int groups = (int)std::max<int64_t>(1, std::min<int64_t>(64, (2048 + tiles - 1) / tiles));
+    while (groups > 1 && (int64_t)groups * t * n * 8 > ((int64_t)256 << 20)) --groups;
+    pl->groups = groups;
+    nsplit = groups;
+    std::vector<int32_t> items, gptr;
+    build_ybar_items(T, groups, items, gptr);
+    for (int k = 1; k <= d; ++k)
+      if ((e = up((void**)&pl->tuples[k], T.tuples[k].data(), T.tuples[k].size())) != hipSuccess)
+        return fail(map_err(e));
+    if ((e = up((void**)&pl->items, items.data(), items.size() * sizeof(int32_t))) != hipSuccess)
       return fail(map_err(e));
-  if ((e = up((void**)&pl->items, items.data(), items.size() * sizeof(int32_t))) != hipSuccess)
+    if ((e = up((void**)&pl->bgptr, gptr.data(), gptr.size() * sizeof(int32_t))) != hipSuccess)
+      return fail(map_err(e));
+  }
+  if ((e = alloc((void**)&pl->part, (size_t)nsplit * t * n * sizeof(double))) != hipSuccess) return fail(map_err(e));
+  if ((e = alloc((void**)&pl->dwpart, (size_t)tiles * n * n * sizeof(double))) != hipSuccess)
     return fail(map_err(e));
-  if ((e = up((void**)&pl->gptr, gptr.data(), gptr.size() * sizeof(int32_t))) != hipSuccess)
-    return fail(map_err(e));
-  if ((e = alloc((void**)&pl->part, (size_t)groups * t * n * sizeof(double))) != hipSuccess) return fail(map_err(e));
-  if ((e = alloc((void**)&pl->Ybar, (size_t)t * n * sizeof(double))) != hipSuccess) return fail(map_err(e));
   *out = pl;
   return CUM_OK;
 }
 
-int cum_loss_plan_grad(cum_loss_plan* pl, const float* X, const float* W, const double* w, double* L, float* dX,
-                       float* dW) {
-  if (!pl || !X || !W || !w || !L || !dX || !dW) return CUM_EINVAL;
-  if (!is_device_ptr(X) || !is_device_ptr(W) || !is_device_ptr(dX) || !is_device_ptr(dW)) return CUM_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// One forward and reverse pass on the plan's buffers (Xp, Wp -> dXp, dWp,
+// the norms in the context), every step a kernel on the plan's stream.
+int loss_pass(cum_loss_plan* pl) {
   cum_ctx* c = pl->c;
   const int n = pl->n, d = pl->d, b = pl->b;
   const int64_t t = pl->t;
   hipStream_t st = pl->st;
-  CUM_TRY(launch_linear(X, W, pl->Y, t, n, st));
+  CUM_TRY(launch_linear(pl->Xp, pl->Wp, pl->Y, t, n, st));
   int rc = cum_recompute(c, pl->Y);
   if (rc != CUM_OK) return rc;
-  std::vector<double> fro((size_t)d + 1), nu((size_t)d + 1);
-  rc = cum_norms(c, fro.data(), nu.data());
-  if (rc != CUM_OK) return rc;
-  double loss = 0.0;
-  for (int k = 1; k <= d; ++k)
-    if (w[k] != 0.0) loss += w[k] * fro[(size_t)k] * fro[(size_t)k];
-  *L = loss;
-  for (int k = 1; k <= d; ++k) {
-    const OrderInfo& o = c->T.ord[k];
-    CUM_TRY(launch_cbar_init(c->C[k], c->mult[k], pl->Cbar[k], o.nelems, o.bk, 2.0 * w[k], st));
+  // the norms (for the loss) are formed on the stream and read at the end
+  if ((rc = flush_norms(c)) != CUM_OK) return rc;
+  {
+    CbarArgs ca{};
+    ca.d = d;
+    for (int k = 1; k <= d; ++k) {
+      ca.off[k] = pl->cbar_base[k];
+      ca.bk[k] = c->T.ord[k].bk;
+      ca.C[k] = c->C[k];
+      ca.mult[k] = c->mult[k];
+    }
+    ca.off[d + 1] = pl->cbar_base[d] + c->T.ord[d].nelems;
+    ca.w = pl->d_w;
+    ca.Cbar = pl->Cbar[1];
+    CUM_TRY(launch_cbar_init(ca, st));
   }
   for (int s = d; s >= 2; --s) {
-    RevArgs ra{};
+    RevBlockArgs ra{};
     ra.b = b;
     ra.bs = c->T.ord[s].bk;
+    ra.tot = pl->rc[s].tot;
     ra.subrank = c->subrank[s];
-    for (int k = 1; k <= d; ++k) {
-      ra.C[k] = c->C[k];
-      ra.Cbar[k] = pl->Cbar[k];
+    ra.Cbar_s = pl->Cbar[s];
+    for (int k = 1; k < s; ++k) {
+      ra.Shi[k] = (const float*)c->s_hi[k];
+      ra.Slo[k] = (const float*)c->s_lo[k];
     }
-    int64_t tot = 1, bs = 1;
-    for (int q = 0; q < s; ++q) { tot *= (b + 1); bs *= b; }
-    const size_t lds = (size_t)(tot - 1 - bs) * 2 * sizeof(double);
-    CUM_TRY(launch_combine_rev(s, ra, c->T.ord[s].nblocks, lds, st));
+    ra.inv_t = 1.0 / (double)t;
+    ra.part = pl->rev_part;
+    CUM_TRY(launch_rev_block(s, ra, c->T.ord[s].nblocks, st));
+    CUM_TRY(launch_rev_collect(pl->rc[s], s, pl->rc_nblocks[s], st));
   }
-  YbarBlockArgs ya{};
-  ya.n = n;
-  ya.b = b;
-  ya.ncols = c->T.nbar * b;
-  ya.t = t;
-  ya.Y = pl->Y;
-  for (int k = 1; k <= d; ++k) {
-    ya.Mbar[k] = pl->Cbar[k];
-    ya.tuples[k] = pl->tuples[k];
+  if (pl->mma) {
+    GbuildArgs ga{};
+    ga.rows = pl->kpad * pl->ncol;
+    ga.ptr = pl->gptr;
+    ga.ent = pl->gent;
+    ga.Mbar = pl->Cbar[1];
+    ga.inv_t = 1.0 / (double)t;
+    ga.G = pl->G;
+    CUM_TRY(launch_gbuild(ga, st));
+    YbarMmaArgs ya{};
+    ya.n = n;
+    ya.ncol = pl->ncol;
+    ya.t = t;
+    ya.kper = (int)(pl->kpad / pl->splits);
+    ya.Y = pl->Y;
+    ya.facs = pl->facs;
+    ya.G = pl->G;
+    ya.part = pl->part;
+    CUM_TRY(launch_ybar_mma(ya, pl->F, pl->splits, st));
+    CUM_TRY(launch_ybar_finish(pl->part, pl->splits, 1.0, pl->Xp, pl->Wp, pl->dXp, pl->dwpart, pl->dWp, t, n, st));
+  } else {
+    YbarBlockArgs ya{};
+    ya.n = n;
+    ya.b = b;
+    ya.ncols = c->T.nbar * b;
+    ya.t = t;
+    ya.Y = pl->Y;
+    for (int k = 1; k <= d; ++k) {
+      ya.Mbar[k] = pl->Cbar[k];
+      ya.tuples[k] = pl->tuples[k];
+    }
+    ya.items = pl->items;
+    ya.gptr = pl->bgptr;
+    ya.part = pl->part;
+    CUM_TRY(launch_ybar_blocks(ya, pl->groups, st));
+    CUM_TRY(launch_ybar_finish(pl->part, pl->groups, 1.0 / (double)t, pl->Xp, pl->Wp, pl->dXp, pl->dwpart,
+                               pl->dWp, t, n, st));
   }
-  ya.items = pl->items;
-  ya.gptr = pl->gptr;
-  ya.part = pl->part;
-  CUM_TRY(launch_ybar_blocks(ya, pl->groups, st));
-  CUM_TRY(launch_ybar_sum(pl->part, pl->groups, t, n, 1.0 / (double)t, pl->Ybar, st));
-  CUM_TRY(launch_dx_dw(pl->Ybar, X, W, dX, dW, t, n, st));
+  return CUM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+// The first call runs the pass eagerly, then captures it into a HIP graph on
+// the plan's stream; later calls copy the inputs in, launch the graph and
+// copy the results out.
+int cum_loss_plan_grad(cum_loss_plan* pl, const float* X, const float* W, const double* w, double* L, float* dX,
+                       float* dW) {
+  if (!pl || !X || !W || !w || !L || !dX || !dW) return CUM_EINVAL;
+  if (!is_device_ptr(X) || !is_device_ptr(W) || !is_device_ptr(dX) || !is_device_ptr(dW)) return CUM_EINVAL;
+  const int n = pl->n, d = pl->d;
+  const int64_t t = pl->t;
+  hipStream_t st = pl->st;
+  for (int k = 0; k <= d; ++k) pl->h_w[k] = w[k];
+  CUM_TRY(hipEventRecord(pl->ev, pl->caller));
+  CUM_TRY(hipStreamWaitEvent(st, pl->ev, 0));
+  CUM_TRY(hipMemcpyAsync(pl->d_w, pl->h_w, (size_t)(d + 1) * sizeof(double), hipMemcpyHostToDevice, st));
+  CUM_TRY(hipMemcpyAsync(pl->Xp, X, (size_t)t * n * sizeof(float), hipMemcpyDeviceToDevice, st));
+  CUM_TRY(hipMemcpyAsync(pl->Wp, W, (size_t)n * n * sizeof(float), hipMemcpyDeviceToDevice, st));
+  if (pl->graph) {
+    CUM_TRY(hipGraphLaunch(pl->graph, st));
+  } else {
+    int rc = loss_pass(pl);
+    if (rc != CUM_OK) return rc;
+    if (!pl->eager_only) {
+      // capture the same pass for the next calls (nothing runs during capture)
+      CUM_TRY(hipStreamSynchronize(st));
+      hipGraph_t g = nullptr;
+      bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) == hipSuccess;
+      const int prc = ok ? loss_pass(pl) : CUM_EDEVICE;
+      ok = (hipStreamEndCapture(st, &g) == hipSuccess) && ok && prc == CUM_OK && g;
+      if (ok) ok = hipGraphInstantiate(&pl->graph, g, nullptr, nullptr, 0) == hipSuccess;
+      if (g) (void)hipGraphDestroy(g);
+      if (!ok) {
+        (void)hipGetLastError();
+        pl->graph = nullptr;
+        pl->eager_only = true;
+      }
+    }
+  }
+  CUM_TRY(hipMemcpyAsync(dX, pl->dXp, (size_t)t * n * sizeof(float), hipMemcpyDeviceToDevice, st));
+  CUM_TRY(hipMemcpyAsync(dW, pl->dWp, (size_t)n * n * sizeof(float), hipMemcpyDeviceToDevice, st));
+  CUM_TRY(hipMemcpyAsync(pl->h_norms, pl->c->norms, (size_t)2 * (d + 1) * sizeof(double), hipMemcpyDeviceToHost,
+                         st));
   CUM_TRY(hipStreamSynchronize(st));
+  double loss = 0.0;
+  for (int k = 1; k <= d; ++k)
+    if (w[k] != 0.0) loss += w[k] * pl->h_norms[k] * pl->h_norms[k];
+  *L = loss;
   return CUM_OK;
 }
 
@@ -1335,6 +1830,7 @@ int cum_loss_grad(int n, int d, int b, const float* X, int64_t t, const float* W
   cum_loss_plan* pl = nullptr;
   int rc = cum_loss_plan_create(&pl, n, d, b, t, hip_stream);
   if (rc != CUM_OK) return rc;
+  pl->eager_only = true;  // one call: nothing to capture for
   rc = cum_loss_plan_grad(pl, X, W, w, L, dX, dW);
   cum_loss_plan_free(pl);
   return rc;

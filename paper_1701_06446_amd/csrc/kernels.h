@@ -103,6 +103,33 @@ bool update_quad_supported(int prec, int n);
 int update_lds_stride(int n);
 // Rows per LDS chunk for a precision and stride (0: not supported).
 int update_chunk_rows(int prec, int str);
+// Split contraction: chunks of one contraction run in one batched launch,
+// each into its own zeroed copy of the running sums (split s: hi at
+// split + 2 s tot, lo at split + (2 s + 1) tot, orders concatenated at
+// off[k]); k_fold_splits then folds the copies into the running sums in
+// chunk order, the same steps a chunk-by-chunk contraction takes, and
+// leaves the copies zeroed for the next split contraction.
+struct FoldArgs {
+  int d, nsplit;
+  int fresh;                         // 1: the running sums start from zero (not read)
+  int64_t tot;                       // state elements of orders 1..d
+  int64_t off[CUM_MAXD + 2];         // first element of order k; off[d+1] = tot
+  void* s_hi[CUM_MAXD + 1];
+  void* s_lo[CUM_MAXD + 1];
+  const void* split;
+};
+hipError_t launch_fold_splits(int prec, const FoldArgs& a, hipStream_t st);
+
+// Zeroes up to ZERO_MAX buffers (sizes in 4-byte words) in one launch: a
+// kernel, so the clearing can sit inside a captured graph.
+constexpr int ZERO_MAX = 16;
+struct ZeroArgs {
+  int count;
+  void* ptr[ZERO_MAX];
+  int64_t words[ZERO_MAX];
+};
+hipError_t launch_zero(const ZeroArgs& a, hipStream_t st);
+
 // e0/e1 (null: none) record the update kernel's own start and end.
 hipError_t launch_update(int prec, int tm, int tn, int kmax, const UpdArgs& a, int nitems, hipStream_t st,
                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);

@@ -1814,6 +1814,63 @@ hipError_t launch_update_batch(int prec, int str, bool vl, int kmax, const UpdAr
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_fold_splits(FoldArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.tot) return;
+  int k = 1;
+  for (int q = 2; q <= a.d; ++q)
+    if (i >= a.off[q]) k = q;
+  const int64_t e = i - a.off[k];
+  T* hp = (T*)a.s_hi[1];
+  T* lp = (T*)a.s_lo[1];
+#pragma unroll
+  for (int q = 2; q <= CUM_MAXD; ++q)
+    if (k == q) {
+      hp = (T*)a.s_hi[q];
+      lp = (T*)a.s_lo[q];
+    }
+  T hi = a.fresh ? T(0) : hp[e], lo = a.fresh ? T(0) : lp[e];
+  T* sp = (T*)a.split;
+  for (int s = 0; s < a.nsplit; ++s) {
+    T* h = sp + (2 * (int64_t)s) * a.tot + i;
+    T* l = sp + (2 * (int64_t)s + 1) * a.tot + i;
+    fold_val(hi, lo, *h);
+    fold_val(hi, lo, *l);
+    *h = T(0);
+    *l = T(0);
+  }
+  hp[e] = hi;
+  lp[e] = lo;
+}
+
+hipError_t launch_fold_splits(int prec, const FoldArgs& a, hipStream_t st) {
+  if (a.tot <= 0 || a.nsplit <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((a.tot + 255) / 256));
+  if (prec == PREC_F64) hipLaunchKernelGGL(k_fold_splits<double>, grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(k_fold_splits<float>, grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_zero(ZeroArgs a) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int q = 0; q < a.count; ++q) {
+    uint32_t* p = (uint32_t*)a.ptr[q];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.words[q]; i += stride) p[i] = 0u;
+  }
+}
+
+hipError_t launch_zero(const ZeroArgs& a, hipStream_t st) {
+  if (a.count <= 0) return hipSuccess;
+  if (a.count > ZERO_MAX) return hipErrorInvalidValue;
+  int64_t mx = 0;
+  for (int q = 0; q < a.count; ++q) mx = a.words[q] > mx ? a.words[q] : mx;
+  const int64_t grid = (mx + 255) / 256 < 2048 ? (mx + 255) / 256 : 2048;
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)grid), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
 // e0/e1 (may be null) take the kernel's own start and end timestamps.
 template <int P, int STR, bool VL>
 static void launch_kmax(int kmax, const UpdArgs& a, int nitems, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {

@@ -101,3 +101,39 @@ def test_autograd_function():
     _, dX, dW = cum.cum_loss_grad(Xd.detach(), Wd.detach(), 4, 4, W8)
     assert torch.allclose(Xd.grad, 2.0 * dX, rtol=1e-6, atol=1e-12)
     assert torch.allclose(Wd.grad, 2.0 * dW, rtol=1e-6, atol=1e-12)
+
+
+def test_bitwise_repeatable():
+    """Two calls on the same inputs return bitwise equal loss and gradients:
+    the reverse combine and Y_bar take every sum in a fixed order."""
+    import paper_1701_06446_amd as cum
+
+    X32, W32 = _inputs()
+    Xd, Wd = torch.from_numpy(X32).cuda(), torch.from_numpy(W32).cuda()
+    L1, dX1, dW1 = cum.cum_loss_grad(Xd, Wd, 4, 4, W8)
+    L2, dX2, dW2 = cum.cum_loss_grad(Xd, Wd, 4, 4, W8)
+    assert L1 == L2
+    assert torch.equal(dX1, dX2) and torch.equal(dW1, dW2)
+
+
+@pytest.mark.parametrize("n,d,b,t", [(10, 5, 2, 3000), (7, 6, 2, 2500), (13, 3, 4, 1999)])
+def test_other_orders_vs_oracle(n, d, b, t):
+    """Orders 3, 5 and 6 (every reverse block size up to 2^6 positions, a
+    ragged last block when b does not divide n, a ragged last row tile),
+    weights on every order from 2 up, against the FP64 oracle."""
+    import paper_1701_06446_amd as cum
+
+    rng = np.random.default_rng(100 * n + d)
+    X = rng.standard_t(6, size=(t, n)) @ (rng.standard_normal((n, n)) / np.sqrt(n))
+    W = np.eye(n) + 0.1 * rng.standard_normal((n, n))
+    X32 = np.ascontiguousarray(X.astype(np.float32))
+    W32 = np.ascontiguousarray(W.astype(np.float32))
+    w8 = {k: 1.0 / k for k in range(2, d + 1)}
+    L, dX, dW = cum.cum_loss_grad(torch.from_numpy(X32).cuda(), torch.from_numpy(W32).cuda(), d, b, w8)
+    Lo, gXo, gWo = adjoint.loss_and_grads(X32.astype(np.float64), W32.astype(np.float64), w8, d=d)
+    dX, dW = dX.cpu().double(), dW.cpu().double()
+    eL = abs(L - Lo) / Lo
+    eX = float((dX - gXo).norm() / gXo.norm())
+    eW = float((dW - gWo).norm() / gWo.norm())
+    print("n=%d d=%d b=%d: loss %.2e dX %.2e dW %.2e" % (n, d, b, eL, eX, eW))
+    assert eL <= 1e-5 and eX <= 1e-5 and eW <= 1e-5
