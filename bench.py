@@ -45,8 +45,8 @@ TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 1e-4}
 # each scaled by the ratio of known bytes to the same counter on a plain
 # device copy.  Valid only for the kernel source they were taken on.
 TRAFFIC = {"prec": "fp32",
-           "kernels_sha256": "2f11412f710bb2cfd1325968bf0d5c17c9c56e7c66e24a6e172bffb96bb6c4ba",
-           "fetch_bytes": 6095.99 * 1024 * 1.99988,   # FETCH_SIZE KiB x (256 MiB / 131078.5 KiB)
+           "kernels_sha256": "87251ea7b3e718ba6639591472e4694a62a55d53789bab293c965b0600b99438",
+           "fetch_bytes": 6094.53 * 1024 * 1.99981,   # FETCH_SIZE KiB x (256 MiB / 131083.44 KiB)
            "write_bytes": 6476.03 * 1024 * 1.00000}   # WRITE_SIZE KiB x (256 MiB / 262144.0 KiB)
 
 
@@ -537,6 +537,8 @@ def main():
     ap.add_argument("--order6-steps", type=int, default=50)
     ap.add_argument("--nu4-runs", type=int, default=100,
                     help="repetitions of the paper-scale nu_4 study (0 skips it)")
+    ap.add_argument("--adjoint-only", type=int, default=0, metavar="CALLS",
+                    help="only time CALLS adjoint calls and print their figures (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -547,6 +549,9 @@ def main():
 
     import streams
 
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": run_adjoint(reps=args.adjoint_only)}))
+        return
     total_steps = max(200, args.warmup + 2 * args.steps + 30)
     s = streams.regime_change_stream(n=N, d=D, b=B, t=T, p=P, steps=total_steps, switch=100)
     paths = [p for p in args.paths.split(",") if p and p != args.prec] + [args.prec]
