@@ -206,22 +206,21 @@ def run_path(path, s, warmup, steps, check, host_leg=False):
     return out
 
 
-def run_batched(steps, warmup, prec="fp32", autotune=True):
+def run_batched(steps, warmup, prec="fp32", autotune=True, reps=5):
     """64 uneven streams (n in 8..96, d in 3..4, t in 1000..20000, p = t/20)
-    updated together by one captured graph; b per stream from the autotuner."""
+    updated together by one captured graph; b per stream from the autotuner's
+    cost model (deterministic)."""
     import torch
 
     import paper_1701_06446_amd as cum
     import streams
     from paper_1701_06446_amd import autotune as at
 
-    ss = streams.batched_streams(m=64, steps=warmup + steps)
+    ss = streams.batched_streams(m=64, steps=warmup + reps * steps)
     t0 = time.perf_counter()
     if autotune:
-        cache = at.load_cache()
         for s in ss:
-            s.b = at.choose_b(s.n, s.d, s.t, s.p, prec, cache=cache)
-        at.save_cache(cache)
+            s.b = at.choose_b(s.n, s.d, s.t, s.p, prec)
     tune_s = time.perf_counter() - t0
     dt = np.float64 if prec == "fp64" else np.float32
     rows = [np.ascontiguousarray(s.rows.astype(dt)) for s in ss]
@@ -239,11 +238,16 @@ def run_batched(steps, warmup, prec="fp32", autotune=True):
     for _ in range(warmup):
         step()
     cum.cum_batch_sync(bt)
-    t1 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    cum.cum_batch_sync(bt)
-    el = time.perf_counter() - t1
+    # `reps` timed blocks of `steps` steps: the median block is reported, the
+    # spread is (max - min) / median over the blocks
+    runs = []
+    for _ in range(reps):
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        cum.cum_batch_sync(bt)
+        runs.append(time.perf_counter() - t1)
+    el = float(np.median(runs))
     rows_per_step = sum(s.p for s in ss)
     flops = sum(2.0 * 2 * s.p * sum(cum.cum_num_elems(s.n, s.b, k) for k in range(1, s.d + 1)) for s in ss)
     flops_distinct = sum(2.0 * 2 * s.p * at.distinct_elements(s.n, s.d) for s in ss)
@@ -255,9 +259,11 @@ def run_batched(steps, warmup, prec="fp32", autotune=True):
     cum.cum_batch_free(bt)
     for c in ctxs:
         cum.cum_free(c)
-    return {"streams": 64, "steps": steps, "warmup": warmup, "prec": prec,
+    return {"streams": 64, "steps": steps, "warmup": warmup, "prec": prec, "timed_blocks": reps,
             "rows_per_s": rows_per_step * steps / el, "updates_per_s": 64 * steps / el,
             "ms_per_step": el / steps * 1e3, "rows_per_step": rows_per_step,
+            "ms_per_step_blocks": [r / steps * 1e3 for r in runs],
+            "spread": (max(runs) - min(runs)) / el,
             "tflops_algorithmic": flops * steps / el / 1e12,
             "tflops_distinct_elements": flops_distinct * steps / el / 1e12,
             "b_choice": {str(b): sum(1 for s in ss if s.b == b) for b in (1, 2, 4, 8)},
@@ -610,8 +616,8 @@ def main():
         print("[bench] adjoint", file=sys.stderr, flush=True)
         line["adjoint"] = run_adjoint()
     if not args.no_batched:
-        print("[bench] batched: 64 streams, 40 steps", file=sys.stderr, flush=True)
-        line["batched"] = run_batched(steps=40, warmup=3)
+        print("[bench] batched: 64 streams, 5 x 30 steps", file=sys.stderr, flush=True)
+        line["batched"] = run_batched(steps=30, warmup=10, reps=5)
         print("[bench] batched: %.3f ms/step" % line["batched"]["ms_per_step"], file=sys.stderr, flush=True)
     if args.nu4_runs > 0:
         print("[bench] nu_4 study: %d runs" % args.nu4_runs, file=sys.stderr, flush=True)

@@ -1019,6 +1019,16 @@ struct cum_batch {
   bool own_stream = false;
   std::vector<UpdArgs> h_upd;
   UpdArgs* d_upd = nullptr;
+  // pinned copies of the argument table, used in turn, each with the event
+  // that marks its copy done (the host waits only when it is kRing steps ahead)
+  static constexpr int kRing = 4;
+  UpdArgs* ring[kRing] = {};
+  hipEvent_t ring_done[kRing] = {};
+  bool ring_used[kRing] = {};
+  int ring_next = 0;
+  // per member, the device allocation its last inputs were found in (the
+  // pointer check is skipped while later inputs stay inside it)
+  std::vector<uintptr_t> alloc_lo, alloc_hi;
   // quad: four-tile workgroups (items in groups of four tiles of one member)
   struct Group { int str; bool vl; int kmax; UpdItem* items; int nitems; int grid; bool quad; };
   std::vector<Group> groups;
@@ -1033,7 +1043,7 @@ struct cum_batch {
   // fused-combine launches, one per (order d, lattice size): a launch's
   // workgroups all reserve its largest lattice, so members of small b do not
   // share the LDS reservation (and occupancy) of a b = 8 member
-  struct LatGroup { int d; int64_t* items; int n; int grid; size_t lds; };
+  struct LatGroup { int d; int64_t* items; int n; int grid; size_t lds; int b; };
   std::vector<LatGroup> lat_groups;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1044,6 +1054,12 @@ struct cum_batch {
 namespace {
 
 void batch_release(cum_batch* bt) {
+  for (int r = 0; r < cum_batch::kRing; ++r) {
+    if (bt->ring_done[r]) (void)hipEventDestroy(bt->ring_done[r]);
+    if (bt->ring[r]) (void)hipHostFree(bt->ring[r]);
+    bt->ring_done[r] = nullptr;
+    bt->ring[r] = nullptr;
+  }
   if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
   if (bt->graph) (void)hipGraphDestroy(bt->graph);
   for (cum_ctx* c : bt->ctx)
@@ -1072,7 +1088,7 @@ int batch_launch_all(cum_batch* bt) {
     else
       CUM_TRY(launch_update_batch(bt->prec, g.str, g.vl, g.kmax, bt->d_upd, g.items, g.nitems, g.grid, bt->stream));
   for (const auto& g : bt->lat_groups)
-    CUM_TRY(launch_combine_lattice_batch(bt->prec, g.d, bt->d_lat, g.items, g.n, g.grid, g.lds, bt->stream));
+    CUM_TRY(launch_combine_lattice_batch(bt->prec, g.d, g.b, bt->d_lat, g.items, g.n, g.grid, g.lds, bt->stream));
   for (int s = 1; s <= CUM_MAXD; ++s)
     CUM_TRY(launch_combine_batch(bt->prec, s, bt->d_comb[s], bt->comb_items[s], bt->ncomb[s], bt->comb_grid[s],
                                  bt->stage_bytes[s], false, bt->stream));
@@ -1122,6 +1138,14 @@ int cum_batch_create(cum_batch** out, cum_ctx* const* ctxs, int m) {
   bt->h_upd.resize((size_t)m);
   for (int i = 0; i < m; ++i) bt->h_upd[(size_t)i] = base_args(ctxs[i]);
   if (bupload(bt, &bt->d_upd, bt->h_upd.data(), bt->h_upd.size()) != hipSuccess) return fail(CUM_ENOMEM);
+  for (int r = 0; r < cum_batch::kRing; ++r)
+    if (hipHostMalloc((void**)&bt->ring[r], (size_t)m * sizeof(UpdArgs), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&bt->ring_done[r], hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(CUM_ENOMEM);
+    }
+  bt->alloc_lo.assign((size_t)m, 0);
+  bt->alloc_hi.assign((size_t)m, 0);
 
   // update items grouped by (LDS stride, vector loader), longest windows first
   std::vector<int> order((size_t)m);
@@ -1177,8 +1201,11 @@ int cum_batch_create(cum_batch** out, cum_ctx* const* ctxs, int m) {
           if (c->lat_lds != lds || c->d != dd) continue;
           for (int64_t blk = 0; blk < c->T.ord[dd].nblocks; ++blk) items.push_back(((int64_t)i << 40) | blk);
         }
-        cum_batch::LatGroup g{dd, nullptr, (int)items.size(), 0, lds};
-        g.grid = std::min(g.n, ncu * 24);
+        int gb = 0;  // every member of the group has this b (the lattice size fixes it)
+        for (int i : order)
+          if (ctxs[i]->lat_lds == lds && ctxs[i]->d == dd) gb = ctxs[i]->b;
+        cum_batch::LatGroup g{dd, nullptr, (int)items.size(), 0, lds, gb};
+        g.grid = g.n;  // one block per workgroup: the hardware keeps every CU full
         if (bupload(bt, &g.items, items.data(), items.size()) != hipSuccess) return fail(CUM_ENOMEM);
         bt->lat_groups.push_back(g);
       }
@@ -1260,9 +1287,28 @@ int cum_batch_update(cum_batch* bt, const void* const* X_new, const void* const*
     if (pi > 0) {
       const void* xo = fifo ? X_new[i] : X_old[i];
       if (!X_new[i] || !xo) return CUM_EINVAL;
-      if (!is_device_ptr(X_new[i]) || !is_device_ptr(xo)) return CUM_EINVAL;
       const bool vl = (c->n * (int)c->x_size) % 16 == 0;
       if (vl && (((uintptr_t)X_new[i] | (uintptr_t)xo) % 16)) return CUM_EINVAL;
+      // device memory: both row blocks inside the allocation the member's
+      // last inputs were found in, or found by a query now
+      const uintptr_t bytes = (uintptr_t)pi * c->n * c->x_size;
+      const uintptr_t a0 = (uintptr_t)X_new[i], a1 = (uintptr_t)xo;
+      uintptr_t& lo = bt->alloc_lo[(size_t)i];
+      uintptr_t& hi = bt->alloc_hi[(size_t)i];
+      const bool inside = lo && a0 >= lo && a0 + bytes <= hi && a1 >= lo && a1 + bytes <= hi;
+      if (!inside) {
+        if (!is_device_ptr(X_new[i]) || !is_device_ptr(xo)) return CUM_EINVAL;
+        hipDeviceptr_t base = nullptr;
+        size_t size = 0;
+        if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)X_new[i]) == hipSuccess && base &&
+            a1 >= (uintptr_t)base && a1 + bytes <= (uintptr_t)base + size) {
+          lo = (uintptr_t)base;
+          hi = (uintptr_t)base + size;
+        } else {
+          (void)hipGetLastError();
+          lo = hi = 0;
+        }
+      }
     }
   }
   for (cum_ctx* c : bt->ctx)
@@ -1286,9 +1332,15 @@ int cum_batch_update(cum_batch* bt, const void* const* X_new, const void* const*
     a.vec = (c->n * (int)c->x_size) % 16 == 0;
     set_fifo(c, a, fifo ? 2 : 0, c->fifo_head);
   }
-  // pageable source: the copy is staged before the call returns
-  CUM_TRY(hipMemcpyAsync(bt->d_upd, bt->h_upd.data(), bt->h_upd.size() * sizeof(UpdArgs), hipMemcpyHostToDevice,
+  // the table goes up from the next pinned slot (its previous copy done)
+  const int r = bt->ring_next;
+  bt->ring_next = (r + 1) % cum_batch::kRing;
+  if (bt->ring_used[r]) CUM_TRY(hipEventSynchronize(bt->ring_done[r]));
+  memcpy(bt->ring[r], bt->h_upd.data(), bt->h_upd.size() * sizeof(UpdArgs));
+  CUM_TRY(hipMemcpyAsync(bt->d_upd, bt->ring[r], bt->h_upd.size() * sizeof(UpdArgs), hipMemcpyHostToDevice,
                          bt->stream));
+  CUM_TRY(hipEventRecord(bt->ring_done[r], bt->stream));
+  bt->ring_used[r] = true;
   CUM_TRY(hipGraphLaunch(bt->exec, bt->stream));
   CUM_TRY(hipEventRecord(bt->done, bt->stream));
   for (int i = 0; i < m; ++i) {

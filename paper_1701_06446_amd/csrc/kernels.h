@@ -143,8 +143,10 @@ hipError_t launch_norms(const NormArgs& a, hipStream_t st);
 // (2^(s-1) - 1 terms) instead of the partition sum of Alg. 4 (B(s) - 1 terms)
 hipError_t launch_combine_lattice(int prec, int d, bool recursion, const LatArgs& a, int64_t nblocks,
                                   size_t lds_bytes, hipStream_t st);
-hipError_t launch_combine_lattice_batch(int prec, int d, const LatArgs* ctxs, const int64_t* items, int nitems,
-                                        int grid, size_t lds_bytes, hipStream_t st);
+// b: the block size every member of the launch shares (b in {2, 4, 8} gets
+// a kernel with b at compile time)
+hipError_t launch_combine_lattice_batch(int prec, int d, int b, const LatArgs* ctxs, const int64_t* items,
+                                        int nitems, int grid, size_t lds_bytes, hipStream_t st);
 
 // Batched launches over several contexts (device-resident argument tables).
 hipError_t launch_update_batch(int prec, int str, bool vl, int kmax, const UpdArgs* ctxs, const UpdItem* items,

@@ -2090,10 +2090,60 @@ static hipError_t launch_lattice_t(int d, bool rec, const LatArgs& a, int64_t nb
   }
 }
 
+// The batched fused combine for members that share one b in {2, 4, 8}: b at
+// compile time, and only that b's code in the kernel (the generic batch
+// kernel carries every b's variant, and the largest sets its registers).
+template <int S, int B, typename St>
+__global__ __launch_bounds__(64) void k_combine_lattice_batch_fix(const LatArgs* __restrict__ ctxs,
+                                                                  const int64_t* __restrict__ items, int nitems) {
+  extern __shared__ __attribute__((aligned(16))) double lat[];
+  for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+    const int64_t w = items[i];
+    const LatArgs& a = ctxs[w >> 40];
+    const int64_t blk = w & ((int64_t(1) << 40) - 1);
+    if (a.rec) lattice_fix<S, B, St, true>(a, blk, lat);
+    else lattice_fix<S, B, St, false>(a, blk, lat);
+    __syncthreads();
+  }
+}
+
+template <int S, typename St>
+static bool launch_lattice_batch_fix(int b, const LatArgs* ctxs, const int64_t* items, int nitems, dim3 g,
+                                     size_t lds, hipStream_t st) {
+  if constexpr (lat_fix_ok(S, 2)) {
+    const dim3 blk(64);
+    switch (b) {
+      case 2: hipLaunchKernelGGL((k_combine_lattice_batch_fix<S, 2, St>), g, blk, lds, st, ctxs, items, nitems); return true;
+      case 4:
+        if constexpr (lat_fix_ok(S, 4)) {
+          hipLaunchKernelGGL((k_combine_lattice_batch_fix<S, 4, St>), g, blk, lds, st, ctxs, items, nitems);
+          return true;
+        }
+        return false;
+      case 8:
+        if constexpr (lat_fix_ok(S, 8)) {
+          hipLaunchKernelGGL((k_combine_lattice_batch_fix<S, 8, St>), g, blk, lds, st, ctxs, items, nitems);
+          return true;
+        }
+        return false;
+      default: return false;
+    }
+  }
+  return false;
+}
+
 template <typename St>
-static hipError_t launch_lattice_batch_t(int d, const LatArgs* ctxs, const int64_t* items, int nitems, int grid,
-                                         size_t lds, hipStream_t st) {
+static hipError_t launch_lattice_batch_t(int d, int b, const LatArgs* ctxs, const int64_t* items, int nitems,
+                                         int grid, size_t lds, hipStream_t st) {
   const dim3 g((unsigned)grid), blk(64);
+  bool done = false;
+  switch (d) {
+    case 2: done = launch_lattice_batch_fix<2, St>(b, ctxs, items, nitems, g, lds, st); break;
+    case 3: done = launch_lattice_batch_fix<3, St>(b, ctxs, items, nitems, g, lds, st); break;
+    case 4: done = launch_lattice_batch_fix<4, St>(b, ctxs, items, nitems, g, lds, st); break;
+    default: break;
+  }
+  if (done) return hipGetLastError();
   switch (d) {
     case 1: hipLaunchKernelGGL((k_combine_lattice_batch<1, St>), g, blk, lds, st, ctxs, items, nitems); break;
     case 2: hipLaunchKernelGGL((k_combine_lattice_batch<2, St>), g, blk, lds, st, ctxs, items, nitems); break;
@@ -2106,12 +2156,12 @@ static hipError_t launch_lattice_batch_t(int d, const LatArgs* ctxs, const int64
   return hipGetLastError();
 }
 
-hipError_t launch_combine_lattice_batch(int prec, int d, const LatArgs* ctxs, const int64_t* items, int nitems,
-                                        int grid, size_t lds_bytes, hipStream_t st) {
+hipError_t launch_combine_lattice_batch(int prec, int d, int b, const LatArgs* ctxs, const int64_t* items,
+                                        int nitems, int grid, size_t lds_bytes, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
   if (lds_bytes > LAT_LDS_BYTES) return hipErrorInvalidValue;
-  if (prec == PREC_F64) return launch_lattice_batch_t<double>(d, ctxs, items, nitems, grid, lds_bytes, st);
-  return launch_lattice_batch_t<float>(d, ctxs, items, nitems, grid, lds_bytes, st);
+  if (prec == PREC_F64) return launch_lattice_batch_t<double>(d, b, ctxs, items, nitems, grid, lds_bytes, st);
+  return launch_lattice_batch_t<float>(d, b, ctxs, items, nitems, grid, lds_bytes, st);
 }
 
 size_t lattice_lds_bytes(int d, int b) {
