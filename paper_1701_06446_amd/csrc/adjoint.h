@@ -49,10 +49,12 @@ struct RevCollectArgs {
 // containing J and j of (multiplicity of j) M_bar (gathered by k_gbuild).
 // Row tiles of 128 over grid.x, K split over grid.y; part[split][l][j] is
 // summed in split order.
+constexpr int YB_MAX_KPER = 4096;  // rows of G per split (their factor words sit in LDS)
+
 struct YbarMmaArgs {
   int n, ncol;                      // ncol = G's padded width (16 per fragment)
   int64_t t;
-  int kper;                         // rows of G per split (a multiple of 16)
+  int kper;                         // rows of G per split (a multiple of 32)
   const float* Y;
   const uint64_t* facs;             // per G row: factor column indices, one byte each
   const double* G;                  // kpad x ncol

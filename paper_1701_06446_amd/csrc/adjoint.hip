@@ -398,35 +398,41 @@ __global__ __launch_bounds__(256) void k_ybar_mma(YbarMmaArgs a) {
   const int n = a.n, np = n + 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t r0 = (int64_t)blockIdx.x * YB_ROWS;
+  // the split's factor words follow the row tile in LDS
+  uint64_t* fl = (uint64_t*)(ys + YB_ROWS * np);
   for (int i = tid; i < YB_ROWS * np; i += 256) {
     const int r = i / np, c = i - r * np;
     const int64_t l = r0 + r;
     ys[i] = c == n ? 1.0 : (l < a.t ? (double)a.Y[l * n + c] : 0.0);
   }
+  for (int i = tid; i < a.kper; i += 256) fl[i] = a.facs[(int64_t)blockIdx.y * a.kper + i];
   __syncthreads();
   const double* yr0 = ys + (wave * 32 + (lane & 15)) * np;
   const double* yr1 = yr0 + 16 * np;
   const int kq = lane >> 4, cl = lane & 15;
   const int64_t k0 = (int64_t)blockIdx.y * a.kper;
   const double* gp = a.G + (k0 + kq) * a.ncol + cl;
-  const uint64_t* fp = a.facs + k0 + kq;
   f64x4v acc[2][NC];
 #pragma unroll
   for (int f = 0; f < 2; ++f)
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[f][c] = f64x4v{0.0, 0.0, 0.0, 0.0};
-  // four k-steps per batch (kper is a multiple of 16); the next batch's
-  // global loads are issued before this batch's products
+  // four k-steps per batch, two batches per iteration (kper is a multiple of
+  // 32); the next batch's global loads are issued before this batch's
+  // products, unconditionally (clamped to the split's last batch, so the
+  // loop has no branch and the load counters stay exact)
   uint64_t fc[2][4];
   double gv[2][4][NC];
   auto load = [&](int kk, int buf) __attribute__((always_inline)) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      fc[buf][u] = fp[kk + 4 * u];
+      fc[buf][u] = fl[kk + 4 * u + kq];
       const double* g = gp + (int64_t)(kk + 4 * u) * a.ncol;
 #pragma unroll
       for (int c = 0; c < NC; ++c) gv[buf][u][c] = g[c * 16];
     }
+    // keep the loads here: left alone, the scheduler sinks each to its use
+    __builtin_amdgcn_sched_barrier(0);
   };
   auto step = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
@@ -446,12 +452,12 @@ __global__ __launch_bounds__(256) void k_ybar_mma(YbarMmaArgs a) {
       }
     }
   };
+  const int last = a.kper - 16;
   load(0, 0);
   for (int kk = 0; kk < a.kper; kk += 32) {
-    if (kk + 16 < a.kper) load(kk + 16, 1);
+    load(kk + 16, 1);
     step(0);
-    if (kk + 16 >= a.kper) break;
-    if (kk + 32 < a.kper) load(kk + 32, 0);
+    load(min(kk + 32, last), 0);
     step(1);
   }
   // lane holds rows lane / 16 + 4 r of each fragment, column lane % 16
@@ -576,7 +582,7 @@ hipError_t launch_gbuild(const GbuildArgs& a, hipStream_t st) {
 
 template <int NC>
 static hipError_t launch_mma_nc(const YbarMmaArgs& a, int F, dim3 grid, hipStream_t st) {
-  const size_t lds = (size_t)YB_ROWS * (a.n + 1) * sizeof(double);
+  const size_t lds = (size_t)YB_ROWS * (a.n + 1) * sizeof(double) + (size_t)a.kper * sizeof(uint64_t);
   switch (F) {
     case 1: hipLaunchKernelGGL((k_ybar_mma<NC, 1>), grid, dim3(256), lds, st, a); break;
     case 2: hipLaunchKernelGGL((k_ybar_mma<NC, 2>), grid, dim3(256), lds, st, a); break;
@@ -589,7 +595,8 @@ static hipError_t launch_mma_nc(const YbarMmaArgs& a, int F, dim3 grid, hipStrea
 }
 
 hipError_t launch_ybar_mma(const YbarMmaArgs& a, int F, int splits, hipStream_t st) {
-  if (a.n < 1 || a.n > 64 || a.kper % 16 || splits < 1) return hipErrorInvalidValue;
+  if (a.n < 1 || a.n > 64 || a.kper % 32 || a.kper < 32 || a.kper > YB_MAX_KPER || splits < 1)
+    return hipErrorInvalidValue;
   const dim3 grid((unsigned)((a.t + YB_ROWS - 1) / YB_ROWS), (unsigned)splits);
   switch (a.ncol / 16) {
     case 1: return launch_mma_nc<1>(a, F, grid, st);

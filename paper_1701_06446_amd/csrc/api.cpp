@@ -1459,8 +1459,8 @@ int build_g_tables(const Tables& T, int n, int d, int64_t splits_max, const int6
   const int64_t K = (int64_t)rows.size();
   const int64_t tiles = (t + 127) / 128;  // row tiles of the Y_bar kernel
   splits = (int)std::max<int64_t>(1, std::min<int64_t>(splits_max, (1024 + tiles - 1) / tiles));
-  kpad = (K + 16 * splits - 1) / (16 * splits) * (16 * splits);
-  if (kpad * ncol > ((int64_t)1 << 24)) return CUM_ESIZE;
+  kpad = (K + 32 * splits - 1) / (32 * splits) * (32 * splits);
+  if (kpad * ncol > ((int64_t)1 << 24) || kpad / splits > YB_MAX_KPER) return CUM_ESIZE;
   facs.assign((size_t)kpad, 0);
   for (int64_t r = 0; r < kpad; ++r) {
     uint64_t f = 0;
