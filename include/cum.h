@@ -98,6 +98,14 @@ int cum_init(cum_ctx **ctx, int n, int d, int b, const void *X, int64_t t, int p
  * deferred: the next update launch forms it in one extra workgroup on a CU
  * its tiles leave idle, and cum_norms, cum_norms_device and cum_sync launch
  * it on its own if it is still pending.
+ * With CUM_PIPELINE=1 in the environment at cum_init, a sliding update of
+ * at most 2048 rows from 16-byte aligned rows (four-tile kernel) is
+ * pipelined instead: the update launch stores the increment, and its fold
+ * into the running sums (the same arithmetic, bitwise equal results), the
+ * combine and the norms run on a stream of the context's own beside the
+ * next update; every other entry point orders that work before its own.
+ * Not while the stream is being captured, for FIFO contexts or batch
+ * members.
  *   X_new  p x n rows entering the window
  *   X_old  p x n rows leaving it; precondition (not checked): these are the
  *          window's p oldest rows

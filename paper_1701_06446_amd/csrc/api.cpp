@@ -92,6 +92,17 @@ struct cum_ctx {
   // them in one extra workgroup, or flush_norms launches them alone
   bool norms_pending = false;
   NormArgs pending_na{};
+  // pipelined sliding updates: the update launch stores its increment in
+  // delta[slot] (slots alternate); on pstream the increment is folded into
+  // the running sums, then the combine and the norms run, beside the next
+  // update.  pipe_active: pstream holds work not yet ordered before stream.
+  hipStream_t pstream = nullptr;
+  void* delta[2] = {};
+  hipEvent_t ev_upd[2] = {}, ev_fold[2] = {}, ev_join = nullptr;
+  bool fold_pending[2] = {};
+  int pipe_slot = 0;
+  bool pipe_active = false;
+  bool pipe_off = true;               // unless CUM_PIPELINE=1 in the environment
   int profile_mask = 0;
   bool no_events = false;             // set during cum_update_noalloc: no profiling events
   int profile_every = 1;              // bracket one launch in this many per class
@@ -175,6 +186,16 @@ void drop_events(cum_ctx* c) {
 }
 
 void release(cum_ctx* c) {
+  if (c->pstream) (void)hipStreamSynchronize(c->pstream);
+  for (int q = 0; q < 2; ++q) {
+    if (c->ev_upd[q]) (void)hipEventDestroy(c->ev_upd[q]);
+    if (c->ev_fold[q]) (void)hipEventDestroy(c->ev_fold[q]);
+    c->ev_upd[q] = c->ev_fold[q] = nullptr;
+  }
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  c->ev_join = nullptr;
+  if (c->pstream) (void)hipStreamDestroy(c->pstream);
+  c->pstream = nullptr;
   drop_events(c);
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
   c->event_pool.clear();
@@ -216,7 +237,9 @@ struct Timed {
   int cls;
   bool own;
   hipEvent_t a = nullptr, b = nullptr;
-  Timed(cum_ctx* ctx, int k, bool own_events = false) : c(ctx), cls(k), own(own_events) {
+  hipStream_t st;
+  Timed(cum_ctx* ctx, int k, bool own_events = false, hipStream_t on = nullptr)
+      : c(ctx), cls(k), own(own_events), st(on ? on : ctx->stream) {
     if (!(c->profile_mask & (1 << cls)) || c->no_events) return;
     if (c->profile_seen[cls]++ % c->profile_every != 0) return;
     a = pooled_event(c);
@@ -227,7 +250,7 @@ struct Timed {
       a = b = nullptr;
       return;
     }
-    if (!own) (void)hipEventRecord(a, c->stream);
+    if (!own) (void)hipEventRecord(a, st);
   }
   hipEvent_t start() const { return a; }
   hipEvent_t stop() const { return b; }
@@ -240,7 +263,7 @@ struct Timed {
       c->event_pool.push_back(b);
       return;
     }
-    if (!own) (void)hipEventRecord(b, c->stream);
+    if (!own) (void)hipEventRecord(b, st);
     c->events.push_back({cls, a, b});
   }
   bool taken = false;
@@ -468,12 +491,13 @@ LatArgs lat_args(const cum_ctx* c) {
   return la;
 }
 
-int run_combine_and_norms(cum_ctx* c) {
+int run_combine_and_norms(cum_ctx* c, hipStream_t st = nullptr) {
+  if (!st) st = c->stream;
   if (c->lat_lds > 0) {
     const LatArgs la = lat_args(c);
-    Timed tm(c, 1);
+    Timed tm(c, 1, false, st);
     CUM_TRY(launch_combine_lattice(c->prec, c->d, c->combine == CUM_COMBINE_RECURSION, la,
-                                   c->T.ord[c->d].nblocks, c->lat_lds, c->stream));
+                                   c->T.ord[c->d].nblocks, c->lat_lds, st));
   }
   for (int s = 1; s <= c->d && c->lat_lds == 0; ++s) {
     CombArgs a{};
@@ -494,11 +518,11 @@ int run_combine_and_norms(cum_ctx* c) {
     a.mult = c->mult[s];
     a.partial = c->partial[s];
     a.rec = c->combine == CUM_COMBINE_RECURSION;
-    Timed tm(c, 1);
+    Timed tm(c, 1, false, st);
     if (combine_split_supported(s, c->b))
-      CUM_TRY(launch_combine_split(c->prec, s, a, c->T.ord[s].nblocks, c->stream));
+      CUM_TRY(launch_combine_split(c->prec, s, a, c->T.ord[s].nblocks, st));
     else
-      CUM_TRY(launch_combine(c->prec, s, a, c->T.ord[s].nblocks, c->stream));
+      CUM_TRY(launch_combine(c->prec, s, a, c->T.ord[s].nblocks, st));
   }
   NormArgs na{};
   na.d = c->d;
@@ -632,6 +656,14 @@ int init_ctx(cum_ctx** out, int n, int d, int b, const void* X, int64_t t, int64
   c->fifo_q = fifo_p ? (int)(t / fifo_p) : 0;
   c->stream = (hipStream_t)hip_stream;
   c->x_size = (prec == CUM_FP64) ? 8 : 4;
+  {
+    // CUM_PIPELINE=1: pipelined sliding updates.  Off by default: where the
+    // update fills every CU (n = 60: one 1024-thread workgroup with 139 KB
+    // of LDS per CU) the side stream's combine and norms only compete with
+    // it, and a step took 67 us instead of 55 us.
+    const char* pe = getenv("CUM_PIPELINE");
+    c->pipe_off = !(pe && pe[0] == '1');
+  }
   c->st_size = (prec == CUM_FP64) ? 8 : 4;
   if (hipGetDevice(&c->device) != hipSuccess) {
     (void)hipGetLastError();
@@ -764,6 +796,115 @@ namespace {
 
 // Shared by cum_update and cum_update_noalloc.  `stage`: where host inputs
 // are copied (nullptr: the context's own buffer, grown on demand).
+// Orders the pipelined work queued on pstream before whatever comes next on
+// the context's stream (every entry point that reads or rewrites the state,
+// the cumulants or the norms calls it first).
+int join_pipe(cum_ctx* c) {
+  if (!c->pipe_active) return CUM_OK;
+  CUM_TRY(hipEventRecord(c->ev_join, c->pstream));
+  CUM_TRY(hipStreamWaitEvent(c->stream, c->ev_join, 0));
+  c->pipe_active = false;
+  return CUM_OK;
+}
+
+// The increments and the side stream of pipelined updates (allocated on the
+// first pipelined update).
+int ensure_pipe(cum_ctx* c) {
+  if (c->pstream) return CUM_OK;
+  const size_t bytes = (size_t)state_elems(c) * c->st_size;
+  size_t used = 0;
+  // zeroed once: the update never writes the elements with a padded index
+  // (b not dividing n), so they must fold in as zero
+  for (int q = 0; q < 2; ++q)
+    if (dalloc(c, &c->delta[q], bytes, &used) != hipSuccess || hipMemset(c->delta[q], 0, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return CUM_ENOMEM;
+    }
+  for (int q = 0; q < 2; ++q)
+    if (hipEventCreateWithFlags(&c->ev_upd[q], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fold[q], hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      return CUM_EDEVICE;
+    }
+  if (hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->pstream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    c->pstream = nullptr;
+    return CUM_EDEVICE;
+  }
+  return CUM_OK;
+}
+
+// A sliding update whose increment, fold, combine and norms overlap the next
+// update: one four-tile launch on the context's stream stores the increment
+// of every stored element in delta[slot]; on pstream the increment is folded
+// into the running sums (the same compensated fold, in the same order, as
+// the update's own), then the combine and the norms.  The next update writes
+// the other slot; the one after waits for this slot's fold.
+bool pipe_eligible(const cum_ctx* c, const char* xn, const char* xo, int64_t p) {
+  if (c->pipe_off || c->fifo_q > 0 || c->no_events || c->batch_done || !c->quad || p < 1 || p > kRowChunk)
+    return false;
+  if ((c->n * c->x_size) % 16 != 0 || (uintptr_t)xn % 16 != 0 || (uintptr_t)xo % 16 != 0) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(c->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return true;
+}
+
+int update_pipelined(cum_ctx* c, const char* xn, const char* xo, int64_t p) {
+  if (int rc = ensure_pipe(c)) return rc;
+  const int slot = c->pipe_slot;
+  c->pipe_slot ^= 1;
+  if (c->fold_pending[slot]) CUM_TRY(hipStreamWaitEvent(c->stream, c->ev_fold[slot], 0));
+  if (c->norms_pending)  // a combine queued on the context's stream before this update
+    if (int rc = flush_norms(c)) return rc;
+  const int64_t tot = state_elems(c);
+  FoldArgs fa{};
+  fa.d = c->d;
+  fa.nsplit = 1;
+  fa.single = 1;
+  fa.tot = tot;
+  UpdArgs a = base_args(c);
+  set_fifo(c, a, 3, 0);
+  int64_t o = 0;
+  for (int k = 1; k <= c->d; ++k) {
+    fa.off[k] = o;
+    fa.s_hi[k] = c->s_hi[k];
+    fa.s_lo[k] = c->s_lo[k];
+    a.s_hi[k] = (char*)c->delta[slot] + (size_t)o * c->st_size;
+    a.s_lo[k] = nullptr;
+    o += c->T.ord[k].nelems;
+  }
+  fa.off[c->d + 1] = tot;
+  fa.split = c->delta[slot];
+  a.xp = xn;
+  a.xm = xo;
+  a.np = (int)p;
+  a.nm = (int)p;
+  a.vec = 1;
+  a.quad = 1;
+  a.items = c->qitems;
+  a.with_norms = 0;
+  {
+    Timed tm(c, 0, true);
+    CUM_TRY(launch_update(c->prec, c->tm, c->tn, c->d, a, c->nitems, c->stream, tm.start(), tm.stop()));
+    tm.launched();
+  }
+  CUM_TRY(hipEventRecord(c->ev_upd[slot], c->stream));
+  CUM_TRY(hipStreamWaitEvent(c->pstream, c->ev_upd[slot], 0));
+  CUM_TRY(launch_fold_splits(c->prec, fa, c->pstream));
+  CUM_TRY(hipEventRecord(c->ev_fold[slot], c->pstream));
+  c->fold_pending[slot] = true;
+  c->pipe_active = true;
+  if (int rc = run_combine_and_norms(c, c->pstream)) return rc;
+  c->norms_pending = false;
+  Timed tn(c, 2, false, c->pstream);
+  CUM_TRY(launch_norms(c->pending_na, c->pstream));
+  return CUM_OK;
+}
+
 int update_impl(cum_ctx* c, const void* X_new, const void* X_old, int64_t p, char* stage) {
   const bool fifo = c->fifo_q > 0;
   const char* xn = (const char*)X_new;
@@ -791,6 +932,8 @@ int update_impl(cum_ctx* c, const void* X_new, const void* X_old, int64_t p, cha
     CUM_TRY(hipStreamWaitEvent(c->stream, c->batch_done, 0));
     c->direct_since_batch = true;
   }
+  if (pipe_eligible(c, xn, xo, p)) return update_pipelined(c, xn, xo, p);
+  if (int rj = join_pipe(c)) return rj;
   int rc;
   if (fifo) {
     rc = run_contraction(c, xn, p, nullptr, 0, 2, c->fifo_head);
@@ -845,6 +988,7 @@ int cum_update_noalloc(cum_ctx* c, const void* X_new, const void* X_old, int64_t
 int cum_recompute(cum_ctx* c, const void* X) {
   if (!c || !X) return CUM_EINVAL;
   if (!c->ready) return CUM_ESTATE;
+  if (int rj = join_pipe(c)) return rj;
   const size_t wbytes = (size_t)c->t * c->n * c->x_size;
   const char* xw = (const char*)X;
   if (!is_device_ptr(X)) {
@@ -888,6 +1032,7 @@ int cum_recompute(cum_ctx* c, const void* X) {
 int cum_get(cum_ctx* c, int k, double* blocks, size_t capacity_elems) {
   if (!c) return CUM_EINVAL;
   if (!c->ready) return CUM_ESTATE;
+  if (int rj = join_pipe(c)) return rj;
   if (k < 1 || k > c->d || !blocks) return CUM_EINVAL;
   const size_t ne = (size_t)c->T.ord[k].nelems;
   if (capacity_elems < ne) return CUM_ESIZE;
@@ -900,6 +1045,7 @@ int cum_get(cum_ctx* c, int k, double* blocks, size_t capacity_elems) {
 int cum_get_moments(cum_ctx* c, int k, double* blocks, size_t capacity_elems) {
   if (!c) return CUM_EINVAL;
   if (!c->ready) return CUM_ESTATE;
+  if (int rj = join_pipe(c)) return rj;
   if (k < 1 || k > c->d || !blocks) return CUM_EINVAL;
   const size_t ne = (size_t)c->T.ord[k].nelems;
   if (capacity_elems < ne) return CUM_ESIZE;
@@ -923,6 +1069,7 @@ int cum_get_moments(cum_ctx* c, int k, double* blocks, size_t capacity_elems) {
 int cum_norms(cum_ctx* c, double* fro, double* nu) {
   if (!c) return CUM_EINVAL;
   if (!c->ready) return CUM_ESTATE;
+  if (int rj = join_pipe(c)) return rj;
   if (!fro || !nu) return CUM_EINVAL;
   CUM_TRY(wait_batch(c));
   if (int rc = flush_norms(c)) return rc;
@@ -939,6 +1086,7 @@ int cum_norms(cum_ctx* c, double* fro, double* nu) {
 int cum_norms_device(cum_ctx* c, const double** dev_ptr) {
   if (!c || !dev_ptr) return CUM_EINVAL;
   if (!c->ready) return CUM_ESTATE;
+  if (int rj = join_pipe(c)) return rj;
   if (int rc = flush_norms(c)) return rc;
   *dev_ptr = c->norms;
   return CUM_OK;
@@ -947,6 +1095,7 @@ int cum_norms_device(cum_ctx* c, const double** dev_ptr) {
 int cum_sync(cum_ctx* c) {
   if (!c) return CUM_EINVAL;
   if (!c->ready) return CUM_ESTATE;
+  if (int rj = join_pipe(c)) return rj;
   CUM_TRY(wait_batch(c));
   if (int rc = flush_norms(c)) return rc;
   CUM_TRY(hipStreamSynchronize(c->stream));
@@ -975,6 +1124,7 @@ int cum_profile_sample(cum_ctx* c, int every) {
 int cum_profile_read(cum_ctx* c, int64_t* launches, double* total_ms) {
   if (!c || !launches || !total_ms) return CUM_EINVAL;
   if (!c->ready) return CUM_ESTATE;
+  if (int rj = join_pipe(c)) return rj;
   CUM_TRY(hipStreamSynchronize(c->stream));
   for (int q = 0; q < 3; ++q) { launches[q] = 0; total_ms[q] = 0.0; }
   for (auto& e : c->events) {
@@ -1122,7 +1272,7 @@ int cum_batch_create(cum_batch** out, cum_ctx* const* ctxs, int m) {
     return rc;
   };
   for (int i = 0; i < m; ++i)
-    if (hipStreamSynchronize(ctxs[i]->stream) != hipSuccess) return fail(CUM_EDEVICE);
+    if (join_pipe(ctxs[i]) != CUM_OK || hipStreamSynchronize(ctxs[i]->stream) != hipSuccess) return fail(CUM_EDEVICE);
   if (hipStreamCreateWithFlags(&bt->stream, hipStreamNonBlocking) != hipSuccess) return fail(CUM_EDEVICE);
   bt->own_stream = true;
   if (hipEventCreateWithFlags(&bt->done, hipEventDisableTiming) != hipSuccess) return fail(CUM_EDEVICE);
@@ -1317,7 +1467,8 @@ int cum_batch_update(cum_batch* bt, const void* const* X_new, const void* const*
       c->direct_since_batch = true;
     }
   for (cum_ctx* c : bt->ctx)
-    if (c->direct_since_batch) {
+    if (c->direct_since_batch || c->pipe_active) {
+      if (int rj = join_pipe(c)) return rj;
       CUM_TRY(hipStreamSynchronize(c->stream));
       c->direct_since_batch = false;
     }

@@ -38,7 +38,10 @@ struct UpdArgs {
   void* s_hi[CUM_MAXD + 1]; // running window sums, compensated pair
   void* s_lo[CUM_MAXD + 1];
   // FIFO of batch increments: 0 off; 1 fold the increment and store it in
-  // snap; 2 fold the increment, fold out the one stored in snap, store it
+  // snap; 2 fold the increment, fold out the one stored in snap, store it.
+  // 3 (four-tile kernel only): store the increment in s_hi[k], without
+  // reading or folding the running sums (k_fold_splits with single = 1
+  // folds it in later)
   int fifo;
   void* snap[CUM_MAXD + 1]; // this update's FIFO slot, one value per stored element
   // 1: one extra workgroup (the last) finishes the norms of the previous
@@ -112,6 +115,7 @@ int update_chunk_rows(int prec, int str);
 struct FoldArgs {
   int d, nsplit;
   int fresh;                         // 1: the running sums start from zero (not read)
+  int single;                        // 1: one array of increments (no lo half, not zeroed)
   int64_t tot;                       // state elements of orders 1..d
   int64_t off[CUM_MAXD + 2];         // first element of order k; off[d+1] = tot
   void* s_hi[CUM_MAXD + 1];

@@ -1583,7 +1583,7 @@ __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
       ph[j] = pl[j] = ps[j] = A1(0);
-      if (eoff[j] >= 0) {
+      if (eoff[j] >= 0 && a.fifo != 3) {
         ph[j] = shi[eoff[j]];
         pl[j] = slo[eoff[j]];
         if (a.fifo == 2) ps[j] = snp[eoff[j]];
@@ -1639,6 +1639,10 @@ __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
       const int e = j * 256 + ltid;
       const A1* rt = red + tile * 4 * 4 * 256;
       const A1 sum = ((rt[e] + rt[4 * 256 + e]) + rt[2 * 4 * 256 + e]) + rt[3 * 4 * 256 + e];
+      if (a.fifo == 3) {  // the increment alone, folded in by a later launch
+        shi[off] = sum;
+        continue;
+      }
       A1 h, l, sn = A1(0);
       if constexpr (EPF) {
         h = ph[j];
@@ -1832,6 +1836,12 @@ __global__ __launch_bounds__(256) void k_fold_splits(FoldArgs a) {
     }
   T hi = a.fresh ? T(0) : hp[e], lo = a.fresh ? T(0) : lp[e];
   T* sp = (T*)a.split;
+  if (a.single) {
+    fold_val(hi, lo, sp[i]);
+    hp[e] = hi;
+    lp[e] = lo;
+    return;
+  }
   for (int s = 0; s < a.nsplit; ++s) {
     T* h = sp + (2 * (int64_t)s) * a.tot + i;
     T* l = sp + (2 * (int64_t)s + 1) * a.tot + i;

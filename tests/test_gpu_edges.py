@@ -200,12 +200,17 @@ def test_profile_sampling_counts():
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_norms_carried_by_next_update(prec):
-    """A step's norms are finished by the next update launch (one extra
-    workgroup) or on demand: after two updates the device buffer holds the
-    first update's norms as that launch formed them, and cum_norms then
-    forms and returns the second's; both against the oracle."""
+@pytest.mark.parametrize("pipelined", [False, True], ids=["serial", "pipelined"])
+def test_norms_carried_by_next_update(prec, pipelined):
+    """Serial updates (CUM_PIPELINE=0): a step's norms are finished by the
+    next update launch (one extra workgroup) or on demand, so after two
+    updates the device buffer holds the first update's norms as that launch
+    formed them, and cum_norms then forms and returns the second's.
+    Pipelined updates form every step's norms on the side stream right
+    after its combine: once the device is idle the buffer holds the second
+    update's.  Both against the oracle."""
     import ctypes
+    import os
 
     import torch
 
@@ -214,7 +219,15 @@ def test_norms_carried_by_next_update(prec):
     n, d, b, t, p = 24, 4, 4, 600, 50
     rows = as_input(_rows(11, t + 2 * p, n), prec)
     dev = to_device(rows)
-    ctx = cum.cum_init(n, d, b, dev[:t], prec=prec)
+    old = os.environ.get("CUM_PIPELINE")
+    os.environ["CUM_PIPELINE"] = "1" if pipelined else "0"
+    try:
+        ctx = cum.cum_init(n, d, b, dev[:t], prec=prec)
+    finally:
+        if old is None:
+            os.environ.pop("CUM_PIPELINE", None)
+        else:
+            os.environ["CUM_PIPELINE"] = old
     ptr = cum.cum_norms_device(ctx)  # the buffer's address does not change
     orc = oracle.SlidingOracle(rows[:t], n, d, b)
     cum.cum_update(ctx, dev[t:t + p], dev[:p])
@@ -229,7 +242,7 @@ def test_norms_carried_by_next_update(prec):
     assert hip.hipMemcpy(ctypes.c_void_p(host.ctypes.data), ctypes.c_void_p(ptr),
                          ctypes.c_size_t(host.nbytes), 2) == 0  # device to host
     tol = max(TOL[prec], 1e-12)
-    np.testing.assert_allclose(host[1:d + 1], fo1[1:], rtol=tol)
+    np.testing.assert_allclose(host[1:d + 1], (fo2 if pipelined else fo1)[1:], rtol=tol)
     fro, nu = cum.cum_norms(ctx)
     np.testing.assert_allclose(fro[1:], fo2[1:], rtol=tol)
     cum.cum_free(ctx)
