@@ -58,3 +58,26 @@ def test_identities():
     assert abs(float((gW * W).sum()) - float((gX * X).sum())) <= 1e-10 * abs(float((gX * X).sum()))
     # cumulants of order >= 2 ignore a common shift of the rows
     assert float(gX.sum(0).abs().max()) <= 1e-10 * float(gX.abs().max())
+
+
+def test_moments_match_the_plain_definition():
+    """The adjoint oracle's moments (products of row-wise Khatri-Rao powers
+    of orders ceil(k/2) and k - ceil(k/2)) against Eq. (mom) written out
+    element by element: M_k[i_1..i_k] = (1/t) sum_l prod_q y[l, i_q], over
+    every multi-index of a small window, orders 1..5."""
+    import itertools
+
+    import numpy as np
+    import torch
+
+    from oracle import adjoint
+
+    rng = np.random.default_rng(7)
+    t, n, d = 40, 3, 5
+    Y = rng.standard_normal((t, n)) + 0.3
+    M = adjoint.moments(torch.from_numpy(Y), d)
+    for k in range(1, d + 1):
+        want = np.zeros((n,) * k)
+        for idx in itertools.product(range(n), repeat=k):
+            want[idx] = np.mean(np.prod(Y[:, list(idx)], axis=1))
+        assert np.allclose(M[k - 1].numpy(), want, rtol=1e-13, atol=1e-15), k
