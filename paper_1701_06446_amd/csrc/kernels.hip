@@ -55,6 +55,28 @@ __device__ __forceinline__ f32x4 mma16(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Two FP32 values v0, v1 (consecutive K indices of one operand) split as
+// v = hi + lo, hi = RNE_bf16(v), lo = RNE_bf16(v - hi), each pair packed in
+// one register the way the bf16 matrix instruction reads it (element 0 in the
+// low half).  One packed conversion per pair for hi and one for lo; hi is
+// widened back exactly by placing its bits in the upper half of a float, and
+// v - hi is exact in FP32.
+__device__ __forceinline__ void split_pair(float v0, float v1, uint32_t& hi, uint32_t& lo) {
+  const uint32_t h = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){v0, v1}, bf16x2));
+  const float h0 = __builtin_bit_cast(float, h << 16);
+  const float h1 = __builtin_bit_cast(float, h & 0xffff0000u);
+  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){v0 - h0, v1 - h1}, bf16x2));
+  hi = h;
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(const uint32_t (&w)[4]) {
+  return __builtin_bit_cast(bf16x8, (u32x4){w[0], w[1], w[2], w[3]});
+}
+
 // Compensated fold of d into the pair (hi, lo): TwoSum then renormalise.
 template <typename T>
 __device__ __forceinline__ void fold_val(T& hi, T& lo, T d) {
@@ -438,39 +460,46 @@ __device__ void upd_body(const UpdArgs& a, const UpdItem& it, char* smem) {
       // a*b ~ ah*bh + ah*bl + al*bh, accumulated in FP32.
 #pragma unroll
       for (int st = 0; st < NKS; ++st) {
-        bf16x8 Ah[TM], Al[TM], Bh[TN], Bl[TN];
+        uint32_t Ah[TM][4], Al[TM][4], Bh[TN][4], Bl[TN][4];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int so = (32 * st + 4 * j) * STR * ES;
+        for (int i = 0; i < 4; ++i) {
+          // rows of K indices 2i and 2i + 1
+          const int so0 = (32 * st + 8 * i) * STR * ES, so1 = so0 + 4 * STR * ES;
 #pragma unroll
           for (int f = 0; f < TM; ++f) {
-            float v = *(const float*)(smem + ao[f][0] + so);
+            float v0 = *(const float*)(smem + ao[f][0] + so0);
+            float v1 = *(const float*)(smem + ao[f][0] + so1);
 #pragma unroll
-            for (int q = 1; q < H; ++q) v *= *(const float*)(smem + ao[f][q] + so);
-            const __bf16 hi = (__bf16)v;
-            Ah[f][j] = hi;
-            Al[f][j] = (__bf16)(v - (float)hi);
+            for (int q = 1; q < H; ++q) {
+              v0 *= *(const float*)(smem + ao[f][q] + so0);
+              v1 *= *(const float*)(smem + ao[f][q] + so1);
+            }
+            split_pair(v0, v1, Ah[f][i], Al[f][i]);
           }
 #pragma unroll
           for (int g = 0; g < TN; ++g) {
-            float v = 1.0f;
+            float v0 = 1.0f, v1 = 1.0f;
             if constexpr (MR > 0) {
-              v = *(const float*)(smem + bo[g][0] + so);
+              v0 = *(const float*)(smem + bo[g][0] + so0);
+              v1 = *(const float*)(smem + bo[g][0] + so1);
 #pragma unroll
-              for (int q = 1; q < MR; ++q) v *= *(const float*)(smem + bo[g][q] + so);
+              for (int q = 1; q < MR; ++q) {
+                v0 *= *(const float*)(smem + bo[g][q] + so0);
+                v1 *= *(const float*)(smem + bo[g][q] + so1);
+              }
             }
-            const __bf16 hi = (__bf16)v;
-            Bh[g][j] = hi;
-            Bl[g][j] = (__bf16)(v - (float)hi);
+            split_pair(v0, v1, Bh[g][i], Bl[g][i]);
           }
         }
 #pragma unroll
         for (int f = 0; f < TM; ++f)
 #pragma unroll
           for (int g = 0; g < TN; ++g) {
-            acc[f][g] = mma16(Al[f], Bh[g], acc[f][g]);
-            acc[f][g] = mma16(Ah[f], Bl[g], acc[f][g]);
-            acc[f][g] = mma16(Ah[f], Bh[g], acc[f][g]);
+            const bf16x8 ah = as_bf16x8(Ah[f]), al = as_bf16x8(Al[f]);
+            const bf16x8 bh = as_bf16x8(Bh[g]), bl = as_bf16x8(Bl[g]);
+            acc[f][g] = mma16(al, bh, acc[f][g]);
+            acc[f][g] = mma16(ah, bl, acc[f][g]);
+            acc[f][g] = mma16(ah, bh, acc[f][g]);
           }
       }
     }
@@ -1480,42 +1509,49 @@ __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
     if constexpr (P == PREC_BF16X3) {
 #pragma unroll
     for (int st = 0; st < G::RG / 32; ++st) {
-      bf16x8 Ah[TM], Al[TM], Bh[TN], Bl[TN];
+      uint32_t Ah[TM][4], Al[TM][4], Bh[TN][4], Bl[TN][4];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int so = (32 * st + 4 * j) * STR * ES + BO;
+      for (int i = 0; i < 4; ++i) {
+        // rows of K indices 2i and 2i + 1
+        const int so0 = (32 * st + 8 * i) * STR * ES + BO, so1 = so0 + 4 * STR * ES;
 #pragma unroll
         for (int f = 0; f < TM; ++f) {
-          float v = *(const float*)(smem + ao[f][0] + so);
+          float v0 = *(const float*)(smem + ao[f][0] + so0);
+          float v1 = *(const float*)(smem + ao[f][0] + so1);
 #pragma unroll
-          for (int q = 1; q < H; ++q) v *= *(const float*)(smem + ao[f][q] + so);
-          const __bf16 hi = (__bf16)v;
-          Ah[f][j] = hi;
-          Al[f][j] = (__bf16)(v - (float)hi);
+          for (int q = 1; q < H; ++q) {
+            v0 *= *(const float*)(smem + ao[f][q] + so0);
+            v1 *= *(const float*)(smem + ao[f][q] + so1);
+          }
+          split_pair(v0, v1, Ah[f][i], Al[f][i]);
         }
 #pragma unroll
         for (int g = 0; g < TN; ++g) {
-          float v = 1.0f;
+          float v0 = 1.0f, v1 = 1.0f;
           if constexpr (MR > 0) {
-            v = *(const float*)(smem + bo[g][0] + so);
+            v0 = *(const float*)(smem + bo[g][0] + so0);
+            v1 = *(const float*)(smem + bo[g][0] + so1);
 #pragma unroll
-            for (int q = 1; q < MR; ++q) v *= *(const float*)(smem + bo[g][q] + so);
+            for (int q = 1; q < MR; ++q) {
+              v0 *= *(const float*)(smem + bo[g][q] + so0);
+              v1 *= *(const float*)(smem + bo[g][q] + so1);
+            }
           }
-          const __bf16 hi = (__bf16)v;
-          Bh[g][j] = hi;
-          Bl[g][j] = (__bf16)(v - (float)hi);
+          split_pair(v0, v1, Bh[g][i], Bl[g][i]);
         }
         // at most two rows' reads in flight (all eight would not fit in
         // registers)
-        if (j & 1) __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
       for (int f = 0; f < TM; ++f)
 #pragma unroll
         for (int g = 0; g < TN; ++g) {
-          acc[f][g] = mma16(Al[f], Bh[g], acc[f][g]);
-          acc[f][g] = mma16(Ah[f], Bl[g], acc[f][g]);
-          acc[f][g] = mma16(Ah[f], Bh[g], acc[f][g]);
+          const bf16x8 ah = as_bf16x8(Ah[f]), al = as_bf16x8(Al[f]);
+          const bf16x8 bh = as_bf16x8(Bh[g]), bl = as_bf16x8(Bl[g]);
+          acc[f][g] = mma16(al, bh, acc[f][g]);
+          acc[f][g] = mma16(ah, bl, acc[f][g]);
+          acc[f][g] = mma16(ah, bh, acc[f][g]);
         }
     }
     }
