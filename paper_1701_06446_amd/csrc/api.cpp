@@ -103,6 +103,9 @@ struct cum_ctx {
   int pipe_slot = 0;
   bool pipe_active = false;
   bool pipe_off = true;               // unless CUM_PIPELINE=1 in the environment
+  // the device allocation the last update's rows were found in: rows inside
+  // it need no pointer query
+  uintptr_t dev_lo = 0, dev_hi = 0;
   int profile_mask = 0;
   bool no_events = false;             // set during cum_update_noalloc: no profiling events
   int profile_every = 1;              // bracket one launch in this many per class
@@ -910,7 +913,25 @@ int update_impl(cum_ctx* c, const void* X_new, const void* X_old, int64_t p, cha
   const char* xn = (const char*)X_new;
   const char* xo = fifo ? nullptr : (const char*)X_old;
   const size_t bytes = (size_t)p * c->n * c->x_size;
-  const bool dn = is_device_ptr(X_new), dob = fifo || is_device_ptr(X_old);
+  const uintptr_t a0 = (uintptr_t)X_new, a1 = (uintptr_t)X_old;
+  const bool cached = c->dev_lo && a0 >= c->dev_lo && a0 + bytes <= c->dev_hi &&
+                      (fifo || (a1 >= c->dev_lo && a1 + bytes <= c->dev_hi));
+  const bool dn = cached || is_device_ptr(X_new);
+  const bool dob = fifo || cached || is_device_ptr(X_old);
+  if (!cached) {
+    c->dev_lo = c->dev_hi = 0;
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (dn && dob) {
+      if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)X_new) == hipSuccess && base &&
+          (fifo || (a1 >= (uintptr_t)base && a1 + bytes <= (uintptr_t)base + size))) {
+        c->dev_lo = (uintptr_t)base;
+        c->dev_hi = (uintptr_t)base + size;
+      } else {
+        (void)hipGetLastError();
+      }
+    }
+  }
   if (!dn || !dob) {
     if (!stage) {
       int rc = ensure_stage(c, 2 * bytes);

@@ -246,3 +246,28 @@ def test_norms_carried_by_next_update(prec, pipelined):
     fro, nu = cum.cum_norms(ctx)
     np.testing.assert_allclose(fro[1:], fo2[1:], rtol=tol)
     cum.cum_free(ctx)
+
+
+def test_inputs_switching_between_allocations():
+    """The library remembers the device allocation the last rows came from
+    and skips the pointer query for rows inside it: rows from that tensor,
+    then host rows, rows from a second device tensor, rows whose X_old lies
+    in another allocation than X_new, and the first tensor again, every step
+    against the oracle."""
+    import paper_1701_06446_amd as cum
+
+    n, d, b, t, p = 12, 4, 4, 300, 40
+    rows = as_input(_rows(11, t + 6 * p, n), "fp64")
+    a = to_device(rows)
+    bdev = to_device(rows.copy())
+    ctx = cum.cum_init(n, d, b, a[:t], prec="fp64")
+    orc = oracle.SlidingOracle(rows[:t], n, d, b)
+    sources = [(a, a), (rows, rows), (bdev, bdev), (a, bdev), (bdev, a), (a, a)]
+    for w, (sn, so) in enumerate(sources, start=1):
+        new, old = slice(t + (w - 1) * p, t + w * p), slice((w - 1) * p, w * p)
+        cum.cum_update(ctx, sn[new], so[old])
+        orc.update(rows[new], rows[old])
+        Co = orc.cumulants()
+        errs = [rel_err(cum.cum_get(ctx, k), Co[k - 1], n, b, k) for k in range(2, d + 1)]
+        assert max(errs) <= TOL["fp64"], (w, errs)
+    cum.cum_free(ctx)
