@@ -1604,10 +1604,14 @@ __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
         }
         B[g] = v;
       }
+      // the k-step's matrix instructions issue back to back at raised wave
+      // priority, the other waves' LDS reads and products fill in around them
+      __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int f = 0; f < TM; ++f)
 #pragma unroll
         for (int g = 0; g < TN; ++g) acc[f][g] = mma(A[f], B[g], acc[f][g]);
+      __builtin_amdgcn_s_setprio(0);
     }
   };
 
