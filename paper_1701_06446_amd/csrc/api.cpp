@@ -287,6 +287,7 @@ void pick_tile(cum_ctx* c) {
 UpdArgs base_args(cum_ctx* c) {
   UpdArgs a{};
   a.n = c->n;
+  a.shl = (16 % c->b == 0) ? 1 : 0;
   a.items = c->items;
   a.zero = c->zero;
   for (int k = 1; k <= c->d; ++k) {

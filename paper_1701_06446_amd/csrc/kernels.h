@@ -48,6 +48,10 @@ struct UpdArgs {
   // combine from its block partials, on a CU the tiles leave idle
   int with_norms;
   NormArgs na;
+  // 1 when b divides 16: the last factor of a left Khatri-Rao column is then
+  // the same for every 16-column fragment of a tile (block v's coordinate
+  // picked by the lane), so a split-bf16x3 tile reads it once per row
+  int shl;
 };
 
 // LDS budget for a combine block's staged lower-order sub-blocks.

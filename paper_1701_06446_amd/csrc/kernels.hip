@@ -1398,7 +1398,9 @@ __device__ __forceinline__ void quad_issue(char* gbuf, const UpdArgs& a, const Q
 
 // TM x TN: the tile's 16 x 16 fragments that lie inside its pivot GEMM (a
 // ragged edge tile multiplies only those)
-template <int P, int H, int MR, int STR, int TM, int TN>
+// SHL (split-bf16x3, a.shl): the tile's fragments share the last factor of
+// their left columns, read once per row for all of them.
+template <int P, int H, int MR, int STR, int TM, int TN, bool SHL = false>
 __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
   constexpr int NF = TM * TN;
   using T = typename Tr<P>::X;
@@ -1514,14 +1516,23 @@ __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
       for (int i = 0; i < 4; ++i) {
         // rows of K indices 2i and 2i + 1
         const int so0 = (32 * st + 8 * i) * STR * ES + BO, so1 = so0 + 4 * STR * ES;
+        float l0 = 1.0f, l1 = 1.0f;
+        if constexpr (SHL) {
+          l0 = *(const float*)(smem + ao[0][H - 1] + so0);
+          l1 = *(const float*)(smem + ao[0][H - 1] + so1);
+        }
 #pragma unroll
         for (int f = 0; f < TM; ++f) {
           float v0 = *(const float*)(smem + ao[f][0] + so0);
           float v1 = *(const float*)(smem + ao[f][0] + so1);
 #pragma unroll
-          for (int q = 1; q < H; ++q) {
+          for (int q = 1; q < (SHL ? H - 1 : H); ++q) {
             v0 *= *(const float*)(smem + ao[f][q] + so0);
             v1 *= *(const float*)(smem + ao[f][q] + so1);
+          }
+          if constexpr (SHL) {
+            v0 *= l0;
+            v1 *= l1;
           }
           split_pair(v0, v1, Ah[f][i], Al[f][i]);
         }
@@ -1707,6 +1718,13 @@ template <int P, int H, int MR, int STR>
 __device__ __forceinline__ void upd_quad_shape(const UpdArgs& a, const UpdItem& it, char* smem) {
   // empty padding tiles (M = N = 0) take the 1 x 1 shape
   const bool m2 = it.M - it.r0 > 16, n2 = it.N - it.c0 > 16;
+  if constexpr (P == PREC_BF16X3 && H >= 2) {
+    if (m2 && a.shl) {
+      if (n2) upd_quad_body<P, H, MR, STR, 2, 2, true>(a, it, smem);
+      else upd_quad_body<P, H, MR, STR, 2, 1, true>(a, it, smem);
+      return;
+    }
+  }
   if (m2 && n2) upd_quad_body<P, H, MR, STR, 2, 2>(a, it, smem);
   else if (m2) upd_quad_body<P, H, MR, STR, 2, 1>(a, it, smem);
   else if (n2) upd_quad_body<P, H, MR, STR, 1, 2>(a, it, smem);
