@@ -50,7 +50,7 @@ struct UpdArgs {
   NormArgs na;
   // 1 when b divides 16: the last factor of a left Khatri-Rao column is then
   // the same for every 16-column fragment of a tile (block v's coordinate
-  // picked by the lane), so a split-bf16x3 tile reads it once per row
+  // picked by the lane), so a tile two fragments high reads it once per row
   int shl;
 };
 

@@ -1398,8 +1398,8 @@ __device__ __forceinline__ void quad_issue(char* gbuf, const UpdArgs& a, const Q
 
 // TM x TN: the tile's 16 x 16 fragments that lie inside its pivot GEMM (a
 // ragged edge tile multiplies only those)
-// SHL (split-bf16x3, a.shl): the tile's fragments share the last factor of
-// their left columns, read once per row for all of them.
+// SHL (a.shl): the tile's fragments share the last factor of their left
+// columns, read once per row for all of them.
 template <int P, int H, int MR, int STR, int TM, int TN, bool SHL = false>
 __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
   constexpr int NF = TM * TN;
@@ -1582,7 +1582,8 @@ __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
 #pragma unroll
       for (int f = 0; f < TM; ++f)
 #pragma unroll
-        for (int q = 0; q < H; ++q) fa[buf][f][q] = *(const T*)(smem + ao[f][q] + so);
+        for (int q = 0; q < H; ++q)
+          if (!SHL || q < H - 1 || f == 0) fa[buf][f][q] = *(const T*)(smem + ao[f][q] + so);
 #pragma unroll
       for (int g = 0; g < TN; ++g)
 #pragma unroll
@@ -1602,7 +1603,7 @@ __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
       for (int f = 0; f < TM; ++f) {
         T v = fa[cur][f][0];
 #pragma unroll
-        for (int q = 1; q < H; ++q) v *= fa[cur][f][q];
+        for (int q = 1; q < H; ++q) v *= fa[cur][SHL && q == H - 1 ? 0 : f][q];
         A[f] = v;
       }
 #pragma unroll
@@ -1718,7 +1719,7 @@ template <int P, int H, int MR, int STR>
 __device__ __forceinline__ void upd_quad_shape(const UpdArgs& a, const UpdItem& it, char* smem) {
   // empty padding tiles (M = N = 0) take the 1 x 1 shape
   const bool m2 = it.M - it.r0 > 16, n2 = it.N - it.c0 > 16;
-  if constexpr (P == PREC_BF16X3 && H >= 2) {
+  if constexpr (H >= 2) {
     if (m2 && a.shl) {
       if (n2) upd_quad_body<P, H, MR, STR, 2, 2, true>(a, it, smem);
       else upd_quad_body<P, H, MR, STR, 2, 1, true>(a, it, smem);
