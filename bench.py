@@ -141,7 +141,7 @@ def run_path(path, s, warmup, steps, check, host_leg=False):
         step()
     torch.cuda.synchronize()
     # timed region: HIP events on the context's stream bracket one update
-    # kernel launch in EVENT_EVERY (each pair adds a gap of a few us)
+    # kernel launch in EVENT_EVERY, the last of each group (each pair adds a gap)
     cum.cum_profile_enable(ctx, ["update"], every=EVENT_EVERY)
     t0 = time.perf_counter()
     for _ in range(steps):

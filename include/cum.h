@@ -205,10 +205,11 @@ int cum_norms_device(cum_ctx *ctx, const double **dev_ptr);
 int cum_profile_enable(cum_ctx *ctx, int on);
 
 /*
- * cum_profile_sample -- bracket only the first of every `every` launches of
+ * cum_profile_sample -- bracket only the last of every `every` launches of
  * each selected class (every >= 1; cum_profile_enable resets it to 1), so
- * that a long timed run pays for few event pairs.  Returns CUM_EINVAL for
- * every < 1.  Does not synchronise.
+ * that a long timed run pays for few event pairs and the first launch after
+ * a synchronisation (which starts on an idle GPU) is not among them unless
+ * every = 1.  Returns CUM_EINVAL for every < 1.  Does not synchronise.
  */
 int cum_profile_sample(cum_ctx *ctx, int every);
 

@@ -244,7 +244,7 @@ struct Timed {
   Timed(cum_ctx* ctx, int k, bool own_events = false, hipStream_t on = nullptr)
       : c(ctx), cls(k), own(own_events), st(on ? on : ctx->stream) {
     if (!(c->profile_mask & (1 << cls)) || c->no_events) return;
-    if (c->profile_seen[cls]++ % c->profile_every != 0) return;
+    if (c->profile_seen[cls]++ % c->profile_every != c->profile_every - 1) return;
     a = pooled_event(c);
     b = pooled_event(c);
     if (!a || !b) {
