@@ -39,10 +39,10 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 EVENT_EVERY = 10  # timed region: one update launch in this many is bracketed by events
 # Untimed steps after the warm-up, before the timed region: after the GPU has
 # been idle (stream set-up, context creation) the shader clock rises over the
-# first ~15 ms of back-to-back updates, and the update's duration falls by
-# ~7 % over its first ~200 launches (fp32 45.3 -> 42.3 us, fp64 85.6 -> 77.8
-# us in a kernel trace); the timed region measures the settled clock.
-SETTLE_STEPS = 200
+# first ~20 ms of back-to-back updates, and the update's duration falls by
+# ~8 % meanwhile (kernel trace: fp32 46.0 -> 42.3 us over ~375 launches, fp64
+# 86.0 -> 77.8 us over ~225); the timed region measures the settled clock.
+SETTLE_STEPS = 500
 TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 1e-4}
 
 
