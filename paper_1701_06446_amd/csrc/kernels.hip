@@ -1554,6 +1554,9 @@ __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
         // registers)
         __builtin_amdgcn_sched_barrier(0);
       }
+      // the matrix instructions at raised wave priority, so that a wave whose
+      // operands are ready keeps the matrix core busy while the others split
+      __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int f = 0; f < TM; ++f)
 #pragma unroll
@@ -1564,6 +1567,7 @@ __device__ void upd_quad_body(const UpdArgs& a, const UpdItem& it, char* smem) {
           acc[f][g] = mma16(ah, bl, acc[f][g]);
           acc[f][g] = mma16(ah, bh, acc[f][g]);
         }
+      __builtin_amdgcn_s_setprio(0);
     }
     }
   };
